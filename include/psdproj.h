@@ -1,0 +1,184 @@
+/*
+ * psdproj -- randomized approximate projection onto the PSD cone on AMD MI355X (gfx950).
+ *
+ * C ABI, version 1.  Implements the two randomized projections of Jones & Anderson,
+ * "Approximate Projection onto the Positive Semidefinite Cone Using Randomization":
+ *
+ *   plain  (Alg. 2): Q = range_finder(X, k, p, q)         (Alg. 1)
+ *                    Q^T X Q = V D V^T
+ *                    P = Q V max(D, 0) V^T Q^T
+ *   scaled (Alg. 3): B = (X + alpha I) / alpha, Q = range_finder(B, k, p, q)
+ *                    Q^T B Q = V D V^T
+ *                    P = alpha Q V (max(D, 1) - I) V^T Q^T
+ *                    alpha is given, or estimated by Alg. 5 (two runs of the power
+ *                    iteration of Alg. 4, N steps each).
+ *
+ * The oversampling parameter l of the paper is called p here; the sketch width is r = k + p.
+ * The range finder orthonormalises after every product with X (subspace iteration), which
+ * spans the same range as the printed (X X^T)^q X Omega (Alg. 1) in exact arithmetic.
+ * All r eigenpairs of the r x r compressed matrix are kept; the clamp decides which
+ * contribute.
+ *
+ * Memory and ownership
+ *   X ("A" below), P, the workspace and result_dev are caller-owned DEVICE memory on the
+ *   current HIP device.  Plans and servers are library-owned opaque handles.  A must stay
+ *   valid and unchanged until the stream has passed the call (or the ticket completed).
+ *   A is read in full and must be exactly symmetric.  Row- and column-major are the same
+ *   for a symmetric matrix; element (i, j) is at A[i * lda + j].
+ *   Precision FP64: A and P hold double.  FP32 and BF16X3: A and P hold float.
+ *   Requirements: lda >= n, ldp >= n, A and P 16-byte aligned.  When lda * sizeof(element)
+ *   is a multiple of 16 the passes over A use 16-byte vector loads; otherwise they fall back
+ *   to element loads (correct, slower).  P may alias A exactly (same pointer and ld): the
+ *   rebuild runs after the last read of A.  Any other overlap is E_INVALID.
+ *
+ * Errors
+ *   Argument errors are returned synchronously and nothing is enqueued.  Errors found on
+ *   the device (non-finite input, alpha <= 0, breakdown) are written to
+ *   result_dev->status after the stream completes; P is then unspecified.  No exception
+ *   or abort crosses the ABI.
+ *
+ * Determinism
+ *   No floating-point atomics are used: a fixed (desc, A) gives bitwise identical P
+ *   whether run alone, in a batch, or through the server.
+ *
+ * Random numbers (Alg. 1 test matrix, Alg. 4 start vectors): Philox4x32-10 with
+ *   key = (seed mod 2^32, seed div 2^32), counter = (c mod 2^32, c div 2^32, stream, 0).
+ *   Element g of a stream uses counter g/2; words (x0,x1) and (x2,x3) give
+ *   u = (((x_hi << 32) | x_lo) >> 11) * 2^-53 + 2^-54, and Box-Muller gives
+ *   sqrt(-2 ln u1) cos(2 pi u2) (even g) or sqrt(-2 ln u1) sin(2 pi u2) (odd g).
+ *   Test-matrix entry (i, j) is element j * n + i of stream 0; the start vectors of the
+ *   first and second power iteration are streams 1 and 2.
+ */
+#ifndef PSDPROJ_H
+#define PSDPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSDPROJ_ABI_VERSION 1
+#define PSDPROJ_MAX_RANK 256   /* k + p limit of this build */
+
+typedef enum {
+    PSDPROJ_OK = 0,
+    PSDPROJ_E_INVALID = 1,     /* bad argument (synchronous) */
+    PSDPROJ_E_ALPHA = 2,       /* scaled: estimated alpha <= 0 or not finite (device) */
+    PSDPROJ_E_NONFINITE = 3,   /* NaN/Inf met in a Gram or compressed matrix (device) */
+    PSDPROJ_E_BREAKDOWN = 4,   /* orthonormalisation lost every direction (device) */
+    PSDPROJ_E_NOMEM = 5,       /* workspace too small or host allocation failed */
+    PSDPROJ_E_BUDGET = 6,      /* server: request larger than the HBM budget */
+    PSDPROJ_E_DEVICE = 7,      /* a HIP runtime call failed */
+    PSDPROJ_E_PENDING = 8,     /* server: ticket not finished yet */
+    PSDPROJ_E_TIMEOUT = 9      /* server: wait timed out */
+} psdproj_status;
+
+typedef enum { PSDPROJ_PLAIN = 0 /* Alg. 2 */, PSDPROJ_SCALED = 1 /* Alg. 3 */ } psdproj_variant;
+
+typedef enum {
+    PSDPROJ_FP64 = 0,    /* A, P, panels in double; FP64 MFMA */
+    PSDPROJ_FP32 = 1,    /* A, P, panels in float; FP32 MFMA, FP32 accumulation */
+    PSDPROJ_BF16X3 = 2   /* A, P in float; products as hi*hi + hi*lo + lo*hi of BF16 splits
+                            on MFMA with FP32 accumulation */
+} psdproj_precision;
+
+/* One projection problem.  Gram/Cholesky factors, the compressed matrix and its
+ * eigensolve are FP64 in every precision. */
+typedef struct {
+    int64_t  n;           /* order of A, >= 1 */
+    int32_t  k;           /* target rank, >= 1 */
+    int32_t  p;           /* oversampling (the paper's l), >= 0; k + p <= min(n, 256) */
+    int32_t  q;           /* power iterations, 0..16 */
+    int32_t  variant;     /* psdproj_variant */
+    int32_t  precision;   /* psdproj_precision */
+    uint64_t seed;        /* Philox key for the test matrix and power-iteration starts */
+    double   alpha;       /* scaled: > 0 use as given; <= 0 estimate with Alg. 5 */
+    int32_t  alpha_iters; /* N of Alg. 4/5 when alpha is estimated, 1..1000 (paper: 10) */
+    uint32_t flags;       /* reserved, must be 0 */
+} psdproj_desc;
+
+/* Written by the device at the end of a run (read it after synchronising). */
+typedef struct {
+    int32_t status;       /* psdproj_status */
+    int32_t r_plus;       /* number of eigenpairs with positive weight */
+    double  alpha_used;   /* scaled: alpha applied (given or estimated); plain: 0 */
+    double  sigma1;       /* scaled with estimation: Alg. 4 on X; else 0 */
+    double  sigma2;       /* scaled with estimation: Alg. 4 on X - sigma1 I; else 0 */
+} psdproj_result;
+
+/* Where intermediate results live inside a run's workspace (byte offsets), for
+ * inspection after the stream has passed the run.  Panels are column-major with
+ * leading dimension panel_ld elements (column j of an n x r panel starts at j*panel_ld). */
+typedef struct {
+    int32_t  r, r_pad, panel_ld, split_k;
+    int32_t  panel_elem_bytes;  /* 8 (FP64) or 4 (FP32, BF16X3) */
+    size_t   omega;      /* test matrix Omega, n x r, panel precision */
+    size_t   q_panel;    /* final orthonormal basis Q, n x r, panel precision */
+    size_t   compressed; /* C = Q^T M(Q) symmetrised, r x r double, ld r_pad, column-major */
+    size_t   evals;      /* eigenvalues of C, ascending, r doubles */
+    size_t   weights;    /* clamped weights of the kept eigenpairs (descending eigenvalue order), r_plus doubles */
+    size_t   factor;     /* W = Q V_keep diag(sqrt(w)), n x r_plus, panel precision; P = W W^T */
+    size_t   power_vec;  /* last power-iteration vector, n doubles */
+    size_t   y_panel;    /* output of the last pass over A, M(Q), n x r, panel precision */
+    size_t   gram;       /* last CholeskyQR Gram matrix, r x r double, ld r_pad, column-major */
+    size_t   total;      /* workspace bytes */
+} psdproj_layout;
+
+typedef struct psdproj_plan_s*   psdproj_plan_t;
+typedef struct psdproj_server_s* psdproj_server_t;
+typedef void*                    psdproj_stream_t;   /* a hipStream_t (NULL = default stream) */
+
+/* Validate desc and fix the tiling and workspace size.  Host only: touches no device.
+ * E_INVALID on a bad descriptor.  *out must be released with psdproj_plan_destroy. */
+psdproj_status psdproj_plan(const psdproj_desc* desc, psdproj_plan_t* out, size_t* workspace_bytes);
+void           psdproj_plan_destroy(psdproj_plan_t plan);
+psdproj_status psdproj_plan_layout(psdproj_plan_t plan, psdproj_layout* out);
+
+/* One projection, enqueued on stream (asynchronous).  workspace: at least the bytes that
+ * psdproj_plan reported, 256-byte aligned, device memory.  result_dev: device memory. */
+psdproj_status psdproj_run(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp,
+                           void* workspace, psdproj_result* result_dev, psdproj_stream_t stream);
+
+/* count independent projections in one grouped launch sequence (each kernel's grid covers
+ * the tiles of all problems).  Arrays have count entries.  workspace_bytes must be at least
+ * what psdproj_batch_workspace reports for the same plans.  Problem i's result goes to
+ * results_dev[i].  Every problem gets the tiling it would get alone, so its P is bitwise
+ * identical to a psdproj_run of the same plan. */
+psdproj_status psdproj_batch_workspace(int32_t count, const psdproj_plan_t* plans, size_t* bytes);
+psdproj_status psdproj_batch(int32_t count, const psdproj_plan_t* plans, const void* const* A,
+                             const int64_t* lda, void* const* P, const int64_t* ldp, void* workspace,
+                             size_t workspace_bytes, psdproj_result* results_dev, psdproj_stream_t stream);
+
+/* Continuous-batching request server on the current device.  Requests are admitted while
+ * the sum of their workspace footprints stays within hbm_budget_bytes and fewer than
+ * max_inflight are in flight; admitted requests advance together, one grouped stage at a
+ * time, and new arrivals join at the next stage boundary.  A and P stay caller-owned. */
+psdproj_status psdproj_server_create(size_t hbm_budget_bytes, int32_t max_inflight, psdproj_server_t* out);
+psdproj_status psdproj_submit(psdproj_server_t server, const psdproj_desc* desc, const void* A, int64_t lda,
+                              void* P, int64_t ldp, uint64_t* ticket);
+/* E_PENDING while in flight; otherwise copies the result to *out (host memory), returns
+ * PSDPROJ_OK, and forgets the ticket. */
+psdproj_status psdproj_poll(psdproj_server_t server, uint64_t ticket, psdproj_result* out);
+psdproj_status psdproj_wait(psdproj_server_t server, uint64_t ticket, psdproj_result* out, double timeout_s);
+/* Per-request timestamps in seconds since server creation: submit, admit, finish. */
+psdproj_status psdproj_server_times(psdproj_server_t server, uint64_t ticket, double* t_submit,
+                                    double* t_admit, double* t_finish);
+void           psdproj_server_destroy(psdproj_server_t server);
+
+/* Utilities (asynchronous on stream, device output). */
+/* Philox4x32-10 words for counters c0 .. c0+count-1 of (seed, stream): out[4*i + w]. */
+psdproj_status psdproj_philox_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count,
+                                    uint32_t* out_dev, psdproj_stream_t stream);
+/* Elements start .. start+count-1 of a Gaussian stream, as double. */
+psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count,
+                                double* out_dev, psdproj_stream_t stream);
+
+const char* psdproj_status_str(psdproj_status status);
+int32_t     psdproj_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSDPROJ_H */

@@ -1,0 +1,191 @@
+"""Randomized approximate PSD projection on AMD MI355X (gfx950).
+
+Thin ctypes binding of libpsdproj (the C ABI in include/psdproj.h).  Functions keep the
+C names; arguments are device pointers, sizes and a HIP stream handle.  PyTorch is used
+only to own device memory and streams: every step of the projection runs in the HIP
+kernels of the library.  Importing this package fails loudly when the library has not
+been built (python -m paper_2410_19208_amd.build) -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "PLAIN", "SCALED", "FP64", "FP32", "BF16X3", "Desc", "Result", "Layout", "PsdprojError",
+    "lib", "psdproj_plan", "psdproj_plan_destroy", "psdproj_plan_layout", "psdproj_run",
+    "psdproj_batch_workspace", "psdproj_batch", "psdproj_server_create", "psdproj_submit",
+    "psdproj_poll", "psdproj_wait", "psdproj_server_times", "psdproj_server_destroy",
+    "psdproj_philox_words", "psdproj_gaussian", "psdproj_status_str", "psdproj_abi_version",
+    "EXPORTED", "LIB_PATH",
+]
+
+PLAIN, SCALED = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
+OK, E_INVALID, E_ALPHA, E_NONFINITE, E_BREAKDOWN, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_TIMEOUT = range(10)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpsdproj.so")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("k", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("alpha", ctypes.c_double), ("alpha_iters", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("r_plus", ctypes.c_int32), ("alpha_used", ctypes.c_double),
+                ("sigma1", ctypes.c_double), ("sigma2", ctypes.c_double)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("r_pad", ctypes.c_int32), ("panel_ld", ctypes.c_int32),
+                ("split_k", ctypes.c_int32), ("panel_elem_bytes", ctypes.c_int32),
+                ("omega", ctypes.c_size_t), ("q_panel", ctypes.c_size_t), ("compressed", ctypes.c_size_t),
+                ("evals", ctypes.c_size_t), ("weights", ctypes.c_size_t), ("factor", ctypes.c_size_t),
+                ("power_vec", ctypes.c_size_t), ("y_panel", ctypes.c_size_t), ("gram", ctypes.c_size_t),
+                ("total", ctypes.c_size_t)]
+
+
+class PsdprojError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {psdproj_status_str(status)} (status {status})")
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_19208_amd.build` "
+                      "(the projection has no non-HIP path)")
+try:
+    # PyTorch bundles its own HIP runtime under the same soname; load it first so that the
+    # library binds to that one and the process holds a single HIP runtime.
+    import torch  # noqa: F401
+except ImportError:  # host-only use (planning, validation) works without PyTorch
+    pass
+lib = ctypes.CDLL(LIB_PATH)
+
+_vp, _i32, _i64, _u32, _u64, _dbl, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+_SIGS = {
+    "psdproj_plan": (_i32, [ctypes.POINTER(Desc), ctypes.POINTER(_vp), ctypes.POINTER(_sz)]),
+    "psdproj_plan_destroy": (None, [_vp]),
+    "psdproj_plan_layout": (_i32, [_vp, ctypes.POINTER(Layout)]),
+    "psdproj_run": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
+    "psdproj_batch_workspace": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_sz)]),
+    "psdproj_batch": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64),
+                             ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp, _vp]),
+    "psdproj_server_create": (_i32, [_sz, _i32, ctypes.POINTER(_vp)]),
+    "psdproj_submit": (_i32, [_vp, ctypes.POINTER(Desc), _vp, _i64, _vp, _i64, ctypes.POINTER(_u64)]),
+    "psdproj_poll": (_i32, [_vp, _u64, ctypes.POINTER(Result)]),
+    "psdproj_wait": (_i32, [_vp, _u64, ctypes.POINTER(Result), _dbl]),
+    "psdproj_server_times": (_i32, [_vp, _u64, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "psdproj_server_destroy": (None, [_vp]),
+    "psdproj_philox_words": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
+    "psdproj_gaussian": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
+    "psdproj_status_str": (ctypes.c_char_p, [_i32]),
+    "psdproj_abi_version": (_i32, []),
+}
+EXPORTED = tuple(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def psdproj_status_str(status: int) -> str:
+    return lib.psdproj_status_str(int(status)).decode()
+
+
+def psdproj_abi_version() -> int:
+    return lib.psdproj_abi_version()
+
+
+def _check(st: int, where: str) -> None:
+    if st != OK:
+        raise PsdprojError(st, where)
+
+
+def psdproj_plan(n, k, p, q=0, variant=PLAIN, precision=FP32, seed=0, alpha=0.0, alpha_iters=10, flags=0):
+    """Returns (plan handle, workspace bytes).  Raises PsdprojError on a bad descriptor."""
+    d = Desc(n, k, p, q, variant, precision, seed, alpha, alpha_iters, flags)
+    h = _vp()
+    ws = _sz()
+    _check(lib.psdproj_plan(ctypes.byref(d), ctypes.byref(h), ctypes.byref(ws)), "psdproj_plan")
+    return h.value, ws.value
+
+
+def psdproj_plan_destroy(plan) -> None:
+    lib.psdproj_plan_destroy(plan)
+
+
+def psdproj_plan_layout(plan) -> Layout:
+    out = Layout()
+    _check(lib.psdproj_plan_layout(plan, ctypes.byref(out)), "psdproj_plan_layout")
+    return out
+
+
+def psdproj_run(plan, A, lda, P, ldp, workspace, result_dev, stream=0) -> None:
+    """All pointers are device addresses (ints); stream is a hipStream_t handle (int)."""
+    _check(lib.psdproj_run(plan, A, lda, P, ldp, workspace, result_dev, stream), "psdproj_run")
+
+
+def psdproj_batch_workspace(plans) -> int:
+    arr = (_vp * len(plans))(*plans)
+    out = _sz()
+    _check(lib.psdproj_batch_workspace(len(plans), arr, ctypes.byref(out)), "psdproj_batch_workspace")
+    return out.value
+
+
+def psdproj_batch(plans, A, lda, P, ldp, workspace, workspace_bytes, results_dev, stream=0) -> None:
+    m = len(plans)
+    _check(lib.psdproj_batch(m, (_vp * m)(*plans), (_vp * m)(*A), (_i64 * m)(*lda), (_vp * m)(*P),
+                             (_i64 * m)(*ldp), workspace, workspace_bytes, results_dev, stream), "psdproj_batch")
+
+
+def psdproj_server_create(hbm_budget_bytes, max_inflight):
+    h = _vp()
+    _check(lib.psdproj_server_create(hbm_budget_bytes, max_inflight, ctypes.byref(h)), "psdproj_server_create")
+    return h.value
+
+
+def psdproj_submit(server, A, lda, P, ldp, n, k, p, q=0, variant=PLAIN, precision=BF16X3, seed=0, alpha=0.0,
+                   alpha_iters=10) -> int:
+    d = Desc(n, k, p, q, variant, precision, seed, alpha, alpha_iters, 0)
+    t = _u64()
+    _check(lib.psdproj_submit(server, ctypes.byref(d), A, lda, P, ldp, ctypes.byref(t)), "psdproj_submit")
+    return t.value
+
+
+def psdproj_poll(server, ticket):
+    """Result, or None while the request is still in flight."""
+    out = Result()
+    st = lib.psdproj_poll(server, ticket, ctypes.byref(out))
+    if st == E_PENDING:
+        return None
+    _check(st, "psdproj_poll")
+    return out
+
+
+def psdproj_wait(server, ticket, timeout_s=60.0) -> Result:
+    out = Result()
+    _check(lib.psdproj_wait(server, ticket, ctypes.byref(out), timeout_s), "psdproj_wait")
+    return out
+
+
+def psdproj_server_times(server, ticket):
+    a, b, c = _dbl(), _dbl(), _dbl()
+    _check(lib.psdproj_server_times(server, ticket, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "psdproj_server_times")
+    return a.value, b.value, c.value
+
+
+def psdproj_server_destroy(server) -> None:
+    lib.psdproj_server_destroy(server)
+
+
+def psdproj_philox_words(seed, stream_id, c0, count, out_dev, stream=0) -> None:
+    _check(lib.psdproj_philox_words(seed, stream_id, c0, count, out_dev, stream), "psdproj_philox_words")
+
+
+def psdproj_gaussian(seed, stream_id, start, count, out_dev, stream=0) -> None:
+    _check(lib.psdproj_gaussian(seed, stream_id, start, count, out_dev, stream), "psdproj_gaussian")

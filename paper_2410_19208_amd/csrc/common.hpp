@@ -1,0 +1,97 @@
+// Internal types shared by the HIP kernels and the host runtime of libpsdproj.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "psdproj.h"
+
+namespace psd {
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+typedef __attribute__((ext_vector_type(2))) double f64x2;
+
+enum Prec : int { F64 = 0, F32 = 1, B3 = 2 };
+
+// Tiling constants.  The pass kernels use 16x16 MFMA tiles; a wave owns RB row blocks of 16
+// rows and every column block of the panel.
+constexpr int WAVE = 64;
+constexpr int PASS_THREADS = 256;             // 4 waves
+constexpr int PASS_BM_F = 128;                // rows per tile, FP32 / BF16X3 (RB = 2)
+constexpr int PASS_BM_D = 64;                 // rows per tile, FP64 (RB = 1)
+constexpr int PASS_BK_F = 64;                 // K per LDS stage, FP32 / BF16X3
+constexpr int PASS_BK_D = 32;                 // K per LDS stage, FP64
+constexpr int PANEL_ALIGN = 64;               // panel leading dimension multiple
+constexpr int RPAD = 32;                      // panel column padding multiple
+constexpr int GRAM_TILE = 32;                 // Gram output tile
+constexpr int GRAM_CHUNK = 1024;              // rows per Gram partial
+constexpr int RB_TILE = 128;                  // rebuild output tile (P)
+constexpr int APPLY_ROWS = 64;                // rows per apply/formw tile
+constexpr int GEMV_ROWS = 32;                 // rows per GEMV workgroup (8 per wave)
+constexpr int NSCAL = 16;
+constexpr int NISCAL = 16;
+
+// scal[] slots
+enum { S_ALPHA = 0, S_SIGMA1 = 1, S_SIGMA2 = 2, S_NRM = 3, S_INV = 4, S_SHIFT = 5, S_TNORM = 6,
+       S_THRESH = 7 };
+// iscal[] slots
+enum { I_STATUS = 0, I_RPLUS = 1, I_NU = 2, I_COUNTER = 3, I_NEWTON = 4, I_NDROP = 5, I_PP = 6 };
+
+// Per-problem descriptor, resident in device memory (workspace header).
+struct Prob {
+  int32_t n, r, rpad, ld;          // order, sketch width, padded width, panel leading dim
+  int32_t k, q, variant, prec;
+  int32_t split, kchunk;           // pass split-K factor and chunk length
+  int32_t ngchunk, alpha_iters;    // Gram row chunks, N of Alg. 4/5
+  int32_t alpha_mode, rwpad;       // 0: alpha given (or plain), 1: estimate; rebuild-factor row stride
+  int32_t npass_tiles, avec;       // avec: rows of A start 16-byte aligned (vector loads allowed)
+  uint64_t seed;
+  double alpha_in;
+  const void* A; int64_t lda;
+  void* P; int64_t ldp;
+  // workspace pointers
+  void* zm; bf16* zhi; bf16* zlo;  // pass operand: master (double/float) and BF16 split
+  void* y;                         // reduced pass output
+  void* part;                      // split-K partials
+  void* q1;                        // first-round CholQR panel
+  void* wf; bf16* whi; bf16* wlo;  // rebuild factor, row-major n x rwpad
+  double* gpart;                   // Gram partials ngchunk x rpad x rpad
+  double* G; double* F; double* C; double* H; double* V;  // rpad x rpad, column-major
+  double* evals; double* tau; double* td; double* te; double* wts; double* xt;  // eig scratch
+  double* vec;                     // power vectors: 2 x ld
+  double* vpart;                   // GEMV block partial sums
+  double* scal;                    // NSCAL doubles
+  int32_t* iscal;                  // NISCAL ints
+  int32_t* drop;                   // rpad flags
+  psdproj_result* res;
+};
+
+// Row (within a 16x16 output block) of accumulator slot v held by a lane of group kg = lane/16:
+// the FP32/BF16 16x16 MFMAs hold rows 4*kg + v, the FP64 16x16x4 MFMA holds rows 4*v + kg.
+template <bool FP64_MFMA>
+__device__ __forceinline__ int acc_row(int kg, int v) { return FP64_MFMA ? 4 * v + kg : 4 * kg + v; }
+
+__device__ __forceinline__ int find_prob(const int* __restrict__ tstart, int nprob, int b) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tstart[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void set_status(const Prob& p, int st) {
+  // First error wins; integer atomic (status is not floating point).
+  atomicCAS(&p.iscal[I_STATUS], 0, st);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace psd

@@ -1,0 +1,342 @@
+// Symmetric eigensolve of the r x r compressed matrix C (Alg. 2 line 2, Alg. 3 line 3) and
+// the clamp (Alg. 2 line 3: max(D, 0); Alg. 3 line 4: alpha (max(D, 1) - I)), in FP64.
+//
+//  k_tridiag : Householder reduction C = Q_H T Q_H^T (one workgroup per problem); also the
+//              Gershgorin interval of T and the Sturm count nu of eigenvalues below the clamp
+//              threshold (0 plain, 1 scaled), so only the r - nu kept eigenpairs get vectors.
+//  k_bisect  : every eigenvalue of T by multisection of Sturm counts, one wave per eigenvalue
+//              (64 trial points per round).
+//  k_invit   : eigenvectors of the kept eigenvalues by inverse iteration on T (tridiagonal LU
+//              with partial pivoting), Gram-Schmidt within clusters of close eigenvalues,
+//              back-transformation by the Householder reflectors, and the clamped weights.
+//              Writes V (column c = c-th largest kept eigenvalue) and F = V diag(sqrt(w)).
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace psd {
+
+constexpr int TRI_THREADS = 256;
+
+// Number of eigenvalues of T below x (Sturm sequence).
+__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int r, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  int c = q < 0.0;
+  for (int i = 1; i < r; ++i) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = (d[i] - x) - e2[i - 1] / q;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(TRI_THREADS) void k_tridiag(const Prob* __restrict__ probs, const int* __restrict__ tstart,
+                                                         int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int r = p.r, rp = p.rpad;
+  double* __restrict__ H = p.H;
+  __shared__ double v[PSDPROJ_MAX_RANK], w[PSDPROJ_MAX_RANK], red[TRI_THREADS / WAVE];
+  __shared__ double s_tau, s_K;
+
+  for (int64_t e = threadIdx.x; e < (int64_t)rp * rp; e += TRI_THREADS) H[e] = p.C[e];
+  __syncthreads();
+
+  for (int j = 0; j + 2 < r; ++j) {
+    // x = H[j+1 .., j]; sigma = ||x[1:]||^2
+    double part = 0.0;
+    for (int i = j + 2 + threadIdx.x; i < r; i += TRI_THREADS) {
+      const double x = H[(int64_t)j * rp + i];
+      part += x * x;
+    }
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sigma = 0.0;
+      for (int wv = 0; wv < TRI_THREADS / WAVE; ++wv) sigma += red[wv];
+      const double alpha = H[(int64_t)j * rp + j + 1];
+      double tau = 0.0, beta = alpha;
+      if (sigma > 0.0) {
+        const double mu = sqrt(alpha * alpha + sigma);
+        beta = (alpha <= 0.0) ? mu : -mu;
+        tau = (beta - alpha) / beta;
+        s_K = 1.0 / (alpha - beta);  // scale of x[1:] into v
+      } else {
+        s_K = 0.0;
+      }
+      s_tau = tau;
+      p.te[j] = beta;
+      p.td[j] = H[(int64_t)j * rp + j];
+      p.tau[j] = tau;
+    }
+    __syncthreads();
+    const double tau = s_tau, sc = s_K;
+    for (int i = threadIdx.x; i < r; i += TRI_THREADS) {
+      double vi = 0.0;
+      if (i == j + 1) vi = 1.0;
+      else if (i > j + 1) vi = H[(int64_t)j * rp + i] * sc;
+      v[i] = vi;
+    }
+    __syncthreads();
+    // store v[j+2..] in column j below the subdiagonal (kept for the back-transformation)
+    for (int i = j + 2 + threadIdx.x; i < r; i += TRI_THREADS) H[(int64_t)j * rp + i] = v[i];
+    if (tau != 0.0) {
+      // p = tau * A2 v (A2 symmetric: row i = column i)
+      for (int i = j + 1 + threadIdx.x; i < r; i += TRI_THREADS) {
+        const double* col = H + (int64_t)i * rp;
+        double s = 0.0;
+        for (int k = j + 1; k < r; ++k) s += col[k] * v[k];
+        w[i] = tau * s;
+      }
+      __syncthreads();
+      // K = tau/2 * p^T v
+      double dp = 0.0;
+      for (int i = j + 1 + threadIdx.x; i < r; i += TRI_THREADS) dp += w[i] * v[i];
+      dp = wave_sum(dp);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dp;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int wv = 0; wv < TRI_THREADS / WAVE; ++wv) s += red[wv];
+        s_K = 0.5 * tau * s;
+      }
+      __syncthreads();
+      const double K = s_K;
+      for (int i = j + 1 + threadIdx.x; i < r; i += TRI_THREADS) w[i] = w[i] - K * v[i];
+      __syncthreads();
+      // A2 -= v w^T + w v^T
+      for (int c = j + 1 + threadIdx.x; c < r; c += TRI_THREADS) {
+        double* col = H + (int64_t)c * rp;
+        const double vc = v[c], wc = w[c];
+        for (int i = j + 1; i < r; ++i) col[i] -= v[i] * wc + w[i] * vc;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (r >= 2) {
+      p.td[r - 2] = H[(int64_t)(r - 2) * rp + r - 2];
+      p.te[r - 2] = H[(int64_t)(r - 2) * rp + r - 1];
+      p.tau[r - 2] = 0.0;
+    }
+    p.td[r - 1] = H[(int64_t)(r - 1) * rp + r - 1];
+    if (r >= 1) p.tau[r - 1] = 0.0;
+    // Gershgorin interval, norm, pivmin, squared off-diagonals
+    double gl = 1e308, gu = -1e308, emax2 = 0.0;
+    for (int i = 0; i < r; ++i) {
+      const double el = (i > 0) ? fabs(p.te[i - 1]) : 0.0;
+      const double er = (i + 1 < r) ? fabs(p.te[i]) : 0.0;
+      gl = fmin(gl, p.td[i] - el - er);
+      gu = fmax(gu, p.td[i] + el + er);
+      if (i + 1 < r) emax2 = fmax(emax2, p.te[i] * p.te[i]);
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    const double slack = 2.0 * 2.220446049250313e-16 * tnorm + 2.0 * pivmin;
+    gl -= slack + 1e-300;
+    gu += slack + 1e-300;
+    for (int i = 0; i + 1 < r; ++i) p.evals[PSDPROJ_MAX_RANK + i] = p.te[i] * p.te[i];  // e^2 scratch
+    p.scal[S_TNORM] = tnorm;
+    p.scal[8] = gl;
+    p.scal[9] = gu;
+    p.scal[10] = pivmin;
+    const double thr = (p.variant == PSDPROJ_SCALED) ? 1.0 : 0.0;
+    p.scal[S_THRESH] = thr;
+    int nu = isfinite(tnorm) ? sturm_count(p.td, p.evals + PSDPROJ_MAX_RANK, r, thr, pivmin) : r;
+    if (nu < 0) nu = 0;
+    if (nu > r) nu = r;
+    p.iscal[I_NU] = nu;
+  }
+}
+
+// One wave per eigenvalue index j (ascending); lane l tests x_l = lo + (hi - lo)(l+1)/65.
+__global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, const int* __restrict__ tstart,
+                                                int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int j = (blockIdx.x - tstart[pi]) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int r = p.r;
+  if (j >= r) return;
+  const double* d = p.td;
+  const double* e2 = p.evals + PSDPROJ_MAX_RANK;
+  const double pivmin = p.scal[10];
+  double lo = p.scal[8], hi = p.scal[9];
+  if (!(isfinite(lo) && isfinite(hi))) {
+    if (lane == 0) p.evals[j] = __builtin_nan("");
+    return;
+  }
+  for (int round = 0; round < 24; ++round) {
+    const double width = hi - lo;
+    const double tol = 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin;
+    if (!(width > 2.0 * tol)) break;
+    const double x = lo + width * (double)(lane + 1) / 65.0;
+    const int c = sturm_count(d, e2, r, x, pivmin);
+    // first lane whose count exceeds j bounds the eigenvalue from above
+    const unsigned long long mask = __ballot(c > j);
+    double nlo = lo, nhi = hi;
+    if (mask) {
+      const int f = __ffsll((long long)mask) - 1;
+      nhi = __shfl(x, f, 64);
+      if (f > 0) nlo = __shfl(x, f - 1, 64);
+    } else {
+      nlo = __shfl(x, 63, 64);
+    }
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) p.evals[j] = 0.5 * (lo + hi);
+}
+
+// Deterministic start vector for inverse iteration (a fixed hash, independent of the seed).
+__device__ __forceinline__ double start_component(int j, int i) {
+  uint32_t h = (uint32_t)(j * 2654435761u) ^ (uint32_t)(i * 2246822519u) ^ 0x9E3779B9u;
+  h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
+  return ((double)h + 0.5) * (1.0 / 4294967296.0) - 0.5;
+}
+
+// One wave per block: every block owns one candidate cluster leader, so block-wide barriers
+// are wave barriers and early exits are block-uniform.
+__global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
+                                                const int* __restrict__ tstart, int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int lane = threadIdx.x;
+  const int r = p.r, rp = p.rpad;
+  const int nu = p.iscal[I_NU];
+  const int j0 = nu + (blockIdx.x - tstart[pi]);
+  const double tnorm = p.scal[S_TNORM];
+  const double thr = p.scal[S_THRESH];
+  const bool scaled = (p.variant == PSDPROJ_SCALED);
+  const double alpha = p.scal[S_ALPHA];
+
+  // weights and r_plus (one thread per problem; read by later kernels)
+  if (blockIdx.x == tstart[pi] && threadIdx.x == 0) {
+    int rplus = 0;
+    for (int jj = r - 1; jj >= nu; --jj) {
+      const double lam = p.evals[jj];
+      const double wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
+      if (wgt > 0.0 && isfinite(wgt)) p.wts[rplus++] = wgt;
+      else break;
+    }
+    for (int c = rplus; c < rp; ++c) p.wts[c] = 0.0;
+    p.iscal[I_RPLUS] = rplus;
+  }
+  if (j0 >= r) return;
+  const double gtol = 1e-5 * tnorm;
+  // only cluster leaders work; a cluster is a run of kept eigenvalues closer than gtol
+  if (j0 > nu && p.evals[j0] - p.evals[j0 - 1] <= gtol) return;
+
+  __shared__ double U0[PSDPROJ_MAX_RANK], U1[PSDPROJ_MAX_RANK], U2[PSDPROJ_MAX_RANK];
+  __shared__ double Lm[PSDPROJ_MAX_RANK], x[PSDPROJ_MAX_RANK], b[PSDPROJ_MAX_RANK];
+  __shared__ int piv[PSDPROJ_MAX_RANK];
+  const double* d = p.td;
+  const double* e = p.te;
+  const double tiny = 2.220446049250313e-16 * fmax(tnorm, 1e-300);
+
+  int jc = j0;
+  do {
+    const double lam = p.evals[jc];
+    // --- LU of T - lam I with partial pivoting (all lanes compute the same values)
+    {
+      double cd = d[0] - lam, cs = (r > 1) ? e[0] : 0.0;
+      for (int i = 0; i + 1 < r; ++i) {
+        const double nd = d[i + 1] - lam;
+        const double ns = (i + 2 < r) ? e[i + 1] : 0.0;
+        const double sb = e[i];
+        if (fabs(cd) >= fabs(sb)) {
+          if (cd == 0.0) cd = tiny;
+          const double m = sb / cd;
+          if (lane == 0) { U0[i] = cd; U1[i] = cs; U2[i] = 0.0; Lm[i] = m; piv[i] = 0; }
+          cd = nd - m * cs;
+          cs = ns;
+        } else {
+          const double m = cd / sb;
+          if (lane == 0) { U0[i] = sb; U1[i] = nd; U2[i] = ns; Lm[i] = m; piv[i] = 1; }
+          cd = cs - m * nd;
+          cs = -m * ns;
+        }
+      }
+      if (cd == 0.0) cd = tiny;
+      if (lane == 0) U0[r - 1] = cd;
+    }
+    for (int i = lane; i < r; i += WAVE) b[i] = start_component(jc, i);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      // --- solve (T - lam I) x = b: forward with row swaps, then back substitution (lane 0)
+      if (lane == 0) {
+        for (int i = 0; i + 1 < r; ++i) {
+          if (piv[i]) { const double t = b[i]; b[i] = b[i + 1]; b[i + 1] = t; }
+          b[i + 1] -= Lm[i] * b[i];
+        }
+        x[r - 1] = b[r - 1] / U0[r - 1];
+        if (r >= 2) x[r - 2] = (b[r - 2] - U1[r - 2] * x[r - 1]) / U0[r - 2];
+        for (int i = r - 3; i >= 0; --i) x[i] = (b[i] - U1[i] * x[i + 1] - U2[i] * x[i + 2]) / U0[i];
+      }
+      __syncthreads();
+      // --- Gram-Schmidt against earlier members of the cluster (stored in xt)
+      for (int m = j0; m < jc; ++m) {
+        const double* xm = p.xt + (int64_t)(m - nu) * rp;
+        double s = 0.0;
+        for (int i = lane; i < r; i += WAVE) s += xm[i] * x[i];
+        s = wave_sum(s);
+        for (int i = lane; i < r; i += WAVE) x[i] -= s * xm[i];
+        __syncthreads();
+      }
+      // --- normalise: b = x / ||x|| (scaled first against overflow)
+      double mx = 0.0;
+      for (int i = lane; i < r; i += WAVE) mx = fmax(mx, fabs(x[i]));
+      for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+      const double inv_mx = (mx > 0.0) ? 1.0 / mx : 0.0;
+      double s2 = 0.0;
+      for (int i = lane; i < r; i += WAVE) { const double t = x[i] * inv_mx; s2 += t * t; }
+      s2 = wave_sum(s2);
+      const double sc = (s2 > 0.0) ? inv_mx / sqrt(s2) : 0.0;
+      for (int i = lane; i < r; i += WAVE) b[i] = x[i] * sc;
+      __syncthreads();
+    }
+    // b holds the unit eigenvector of T; keep it for later cluster members
+    double* xs = p.xt + (int64_t)(jc - nu) * rp;
+    for (int i = lane; i < r; i += WAVE) xs[i] = b[i];
+    // --- back-transform u = H_0 H_1 ... H_{r-3} b
+    for (int jh = r - 3; jh >= 0; --jh) {
+      const double tau = p.tau[jh];
+      if (tau == 0.0) continue;
+      const double* col = p.H + (int64_t)jh * rp;
+      double s = 0.0;
+      for (int i = jh + 1 + lane; i < r; i += WAVE) s += ((i == jh + 1) ? 1.0 : col[i]) * b[i];
+      s = wave_sum(s) * tau;
+      __syncthreads();
+      for (int i = jh + 1 + lane; i < r; i += WAVE) b[i] -= s * ((i == jh + 1) ? 1.0 : col[i]);
+      __syncthreads();
+    }
+    // --- store: column c = r-1-jc (descending eigenvalue order)
+    const int c = r - 1 - jc;
+    const double wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
+    const double sw = (wgt > 0.0 && isfinite(wgt)) ? sqrt(wgt) : 0.0;
+    for (int i = lane; i < rp; i += WAVE) {
+      const double u = (i < r) ? b[i] : 0.0;
+      p.V[(int64_t)c * rp + i] = u;
+      p.F[(int64_t)c * rp + i] = u * sw;
+    }
+    __syncthreads();
+    ++jc;
+  } while (jc < r && p.evals[jc] - p.evals[jc - 1] <= gtol);
+  (void)thr;
+}
+
+int tiles_bisect(const Prob& p) { return (p.r + 3) / 4; }
+int tiles_invit(const Prob& p) { return p.r; }
+
+void launch_tridiag(const Launch& L) {
+  hipLaunchKernelGGL(k_tridiag, dim3(L.grid), dim3(TRI_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+}
+void launch_bisect(const Launch& L) {
+  hipLaunchKernelGGL(k_bisect, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob);
+}
+void launch_invit(const Launch& L) {
+  hipLaunchKernelGGL(k_invit, dim3(L.grid), dim3(WAVE), 0, L.stream, L.probs, L.tstart, L.nprob);
+}
+
+}  // namespace psd

@@ -1,0 +1,130 @@
+// Philox4x32-10 test matrices and start vectors (Alg. 1 line 1, Alg. 4 line 1).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (c0,c1,c2,c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+// with the key bumped by the Weyl constants between rounds.  Counter/key/element
+// conventions are those documented in psdproj.h.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace psd {
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd) { k0 += W0; k1 += W1; }
+    uint64_t p0 = (uint64_t)M0 * c.x;
+    uint64_t p1 = (uint64_t)M1 * c.z;
+    U4 o;
+    o.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    o.y = (uint32_t)p1;
+    o.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    o.w = (uint32_t)p0;
+    c = o;
+  }
+  return c;
+}
+
+__device__ __forceinline__ U4 philox_at(uint64_t seed, uint32_t stream, uint64_t c) {
+  U4 ctr{(uint32_t)c, (uint32_t)(c >> 32), stream, 0u};
+  return philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo) {
+  uint64_t v = ((uint64_t)hi << 32) | (uint64_t)lo;
+  return (double)(v >> 11) * 0x1.0p-53 + 0x1.0p-54;
+}
+
+// Element g of a Gaussian stream: Box-Muller on the two uniforms of counter g/2.
+__device__ __forceinline__ double gauss_at(uint64_t seed, uint32_t stream, uint64_t g) {
+  U4 w = philox_at(seed, stream, g >> 1);
+  double u1 = unit53(w.x, w.y);
+  double u2 = unit53(w.z, w.w);
+  double rad = sqrt(-2.0 * log(u1));
+  double ang = 2.0 * M_PI * u2;
+  return (g & 1) ? rad * sin(ang) : rad * cos(ang);
+}
+
+__device__ __forceinline__ void split_bf16(float x, bf16& hi, bf16& lo) {
+  hi = (bf16)x;
+  lo = (bf16)(x - (float)hi);
+}
+
+// Omega panel (column-major, ld), zero outside n x r.
+__global__ __launch_bounds__(256) void k_omega(const Prob* __restrict__ probs, const int* __restrict__ tstart,
+                                               int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int64_t total = (int64_t)p.rpad * p.ld;
+  const int64_t base = (int64_t)(blockIdx.x - tstart[pi]) * 1024;
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int64_t idx = base + e;
+    if (idx >= total) break;
+    const int j = (int)(idx / p.ld), i = (int)(idx % p.ld);
+    double v = 0.0;
+    if (i < p.n && j < p.r) v = gauss_at(p.seed, 0u, (uint64_t)j * (uint64_t)p.n + (uint64_t)i);
+    if (p.prec == F64) {
+      ((double*)p.zm)[idx] = v;
+    } else {
+      float f = (float)v;
+      ((float*)p.zm)[idx] = f;
+      if (p.prec == B3) split_bf16(f, p.zhi[idx], p.zlo[idx]);
+    }
+  }
+}
+
+// Start vector of a power iteration (stream 1 or 2) into vec[0..ld), and reset the
+// per-iteration scalars: inverse norm 1 (the first product uses the raw Gaussian vector).
+__global__ __launch_bounds__(256) void k_power_init(const Prob* __restrict__ probs, const int* __restrict__ tstart,
+                                                    int nprob, int which) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int base = (blockIdx.x - tstart[pi]) * 1024;
+  double* v = p.vec + (int64_t)(p.iscal[I_PP] & 1) * p.ld;   // the vector the next product reads
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int i = base + e;
+    if (i >= p.ld) break;
+    v[i] = (i < p.n) ? gauss_at(p.seed, (uint32_t)(1 + which), (uint64_t)i) : 0.0;
+  }
+  if (blockIdx.x == tstart[pi] && threadIdx.x == 0) {
+    p.scal[S_INV] = 1.0;
+    p.scal[S_SHIFT] = (which == 0) ? 0.0 : p.scal[S_SIGMA1];
+  }
+}
+
+__global__ void k_words(uint64_t seed, uint32_t stream, uint64_t c0, int64_t count, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  U4 w = philox_at(seed, stream, c0 + (uint64_t)i);
+  out[4 * i + 0] = w.x;
+  out[4 * i + 1] = w.y;
+  out[4 * i + 2] = w.z;
+  out[4 * i + 3] = w.w;
+}
+
+__global__ void k_gauss(uint64_t seed, uint32_t stream, uint64_t start, int64_t count, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  out[i] = gauss_at(seed, stream, start + (uint64_t)i);
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_omega(const Launch& L) {
+  hipLaunchKernelGGL(k_omega, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob);
+}
+void launch_power_init(const Launch& L, int which) {
+  hipLaunchKernelGGL(k_power_init, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob, which);
+}
+void launch_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count, uint32_t* out, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_words, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, seed, stream_id, c0, count, out);
+}
+void launch_gauss(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count, double* out, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_gauss, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, seed, stream_id, start, count, out);
+}
+
+}  // namespace psd

@@ -1,0 +1,494 @@
+// Host runtime of libpsdproj: plans, workspace layout, the grouped launch schedule and the
+// C ABI of psdproj.h (single runs and batches; the request server lives in server.cpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+namespace psd {
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------------------ planning
+psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
+  if (!d) return PSDPROJ_E_INVALID;
+  if (d->n < 1 || d->n > (1 << 20)) return PSDPROJ_E_INVALID;
+  if (d->k < 1 || d->p < 0) return PSDPROJ_E_INVALID;
+  const int64_t r = (int64_t)d->k + d->p;
+  if (r > d->n || r > PSDPROJ_MAX_RANK) return PSDPROJ_E_INVALID;
+  if (d->q < 0 || d->q > 16) return PSDPROJ_E_INVALID;
+  if (d->variant != PSDPROJ_PLAIN && d->variant != PSDPROJ_SCALED) return PSDPROJ_E_INVALID;
+  if (d->precision < PSDPROJ_FP64 || d->precision > PSDPROJ_BF16X3) return PSDPROJ_E_INVALID;
+  if (d->flags != 0) return PSDPROJ_E_INVALID;
+  int alpha_mode = 0;
+  if (d->variant == PSDPROJ_SCALED) {
+    if (std::isnan(d->alpha) || std::isinf(d->alpha)) return PSDPROJ_E_INVALID;
+    if (d->alpha <= 0.0) {
+      if (d->alpha_iters < 1 || d->alpha_iters > 1000) return PSDPROJ_E_INVALID;
+      alpha_mode = 1;
+    }
+  }
+  pl.d = *d;
+  const int n = (int)d->n;
+  pl.r = (int)r;
+  pl.rpad = rup(pl.r, RPAD);
+  pl.ld = rup(n, 128);
+  pl.prec = d->precision;
+  pl.es = (pl.prec == F64) ? 8 : 4;
+  pl.ncb = pl.rpad / 16;
+  pl.alpha_mode = alpha_mode;
+  // split-K: enough workgroups to fill 256 CUs twice, at most 8 (one K chunk per XCD)
+  const int bm = (pl.prec == F64) ? PASS_BM_D : PASS_BM_F;
+  const int bk = (pl.prec == F64) ? PASS_BK_D : PASS_BK_F;
+  const int mt = (n + bm - 1) / bm;
+  int split = std::min(8, std::max(1, (512 + mt - 1) / mt));
+  int kchunk = rup((n + split - 1) / split, bk);
+  split = (n + kchunk - 1) / kchunk;
+  pl.split = split;
+  pl.kchunk = kchunk;
+  pl.ngchunk = (pl.ld + GRAM_CHUNK - 1) / GRAM_CHUNK;
+  pl.rwpad = pl.rpad;
+
+  // workspace region of one problem
+  const size_t P = (size_t)pl.rpad * pl.ld;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = al256(o + bytes); return at; };
+  pl.o_zm = take(P * pl.es);
+  pl.o_zhi = (pl.prec == B3) ? take(P * 2) : 0;
+  pl.o_zlo = (pl.prec == B3) ? take(P * 2) : 0;
+  pl.o_y = take(P * pl.es);
+  pl.o_part = take((size_t)split * P * pl.es);
+  pl.o_q1 = take(P * pl.es);
+  pl.o_wf = take((size_t)pl.ld * pl.rwpad * pl.es);
+  pl.o_whi = (pl.prec == B3) ? take((size_t)pl.ld * pl.rwpad * 2) : 0;
+  pl.o_wlo = (pl.prec == B3) ? take((size_t)pl.ld * pl.rwpad * 2) : 0;
+  const size_t RR = (size_t)pl.rpad * pl.rpad * 8;
+  pl.o_gpart = take((size_t)pl.ngchunk * RR);
+  pl.o_G = take(RR);
+  pl.o_F = take(RR);
+  pl.o_C = take(RR);
+  pl.o_H = take(RR);
+  pl.o_V = take(RR);
+  pl.o_xt = take(RR);
+  pl.o_evals = take(2 * PSDPROJ_MAX_RANK * 8);
+  pl.o_tau = take(PSDPROJ_MAX_RANK * 8);
+  pl.o_td = take(PSDPROJ_MAX_RANK * 8);
+  pl.o_te = take(PSDPROJ_MAX_RANK * 8);
+  pl.o_wts = take(PSDPROJ_MAX_RANK * 8);
+  pl.o_vec = take((size_t)2 * pl.ld * 8);
+  pl.o_vpart = take((size_t)(pl.ld / GEMV_ROWS + 1) * 8);
+  pl.o_scal = take(NSCAL * 8);
+  pl.o_iscal = take(NISCAL * 4);
+  pl.o_drop = take(PSDPROJ_MAX_RANK * 4);
+  pl.region = o;
+  // header for a single run
+  Schedule s;
+  const Plan* one = &pl;
+  build_schedule(&one, 1, s);
+  pl.header_single = s.header_bytes;
+  return PSDPROJ_OK;
+}
+
+Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda, void* P, int64_t ldp,
+               psdproj_result* res) {
+  Prob p;
+  std::memset(&p, 0, sizeof(p));
+  const psdproj_desc& d = pl.d;
+  p.n = (int)d.n; p.r = pl.r; p.rpad = pl.rpad; p.ld = pl.ld;
+  p.k = d.k; p.q = d.q; p.variant = d.variant; p.prec = pl.prec;
+  p.split = pl.split; p.kchunk = pl.kchunk; p.ngchunk = pl.ngchunk;
+  p.alpha_iters = d.alpha_iters; p.alpha_mode = pl.alpha_mode; p.rwpad = pl.rwpad;
+  p.seed = d.seed; p.alpha_in = d.alpha;
+  p.A = A; p.lda = lda; p.P = P; p.ldp = ldp;
+  p.avec = ((lda * pl.es) % 16 == 0) ? 1 : 0;
+  auto at = [&](size_t off) { return (void*)(region + off); };
+  p.zm = at(pl.o_zm);
+  p.zhi = (bf16*)(pl.prec == B3 ? at(pl.o_zhi) : nullptr);
+  p.zlo = (bf16*)(pl.prec == B3 ? at(pl.o_zlo) : nullptr);
+  p.y = at(pl.o_y); p.part = at(pl.o_part); p.q1 = at(pl.o_q1);
+  p.wf = at(pl.o_wf);
+  p.whi = (bf16*)(pl.prec == B3 ? at(pl.o_whi) : nullptr);
+  p.wlo = (bf16*)(pl.prec == B3 ? at(pl.o_wlo) : nullptr);
+  p.gpart = (double*)at(pl.o_gpart);
+  p.G = (double*)at(pl.o_G); p.F = (double*)at(pl.o_F); p.C = (double*)at(pl.o_C);
+  p.H = (double*)at(pl.o_H); p.V = (double*)at(pl.o_V); p.xt = (double*)at(pl.o_xt);
+  p.evals = (double*)at(pl.o_evals); p.tau = (double*)at(pl.o_tau);
+  p.td = (double*)at(pl.o_td); p.te = (double*)at(pl.o_te); p.wts = (double*)at(pl.o_wts);
+  p.vec = (double*)at(pl.o_vec); p.vpart = (double*)at(pl.o_vpart);
+  p.scal = (double*)at(pl.o_scal); p.iscal = (int32_t*)at(pl.o_iscal); p.drop = (int32_t*)at(pl.o_drop);
+  p.res = res;
+  p.npass_tiles = tiles_pass(p);
+  return p;
+}
+
+// ------------------------------------------------------------------------------ schedule
+// A problem's stage list; problems of a batch are aligned step by step, inactive ones get
+// zero tiles.  Pass and rebuild kernels are templated on (precision, column blocks), so the
+// problems are ordered by that key and those stages launch once per key group.
+static bool active_in(const Plan& pl, const Stage& st) {
+  switch (st.when) {
+    case W_ALL: return true;
+    case W_ALPHA: return pl.alpha_mode == 1;
+    case W_ALPHA_ITER: return pl.alpha_mode == 1 && st.iter < pl.d.alpha_iters;
+    case W_POWER: return st.iter < pl.d.q;
+  }
+  return false;
+}
+
+static int stage_tiles(const Prob& p, int kind) {
+  switch (kind) {
+    case K_SETUP: case K_ALPHA: case K_CHOL: case K_TRIDIAG: case K_FINAL: return 1;
+    case K_OMEGA: return tiles_omega(p);
+    case K_PINIT: return tiles_vec(p);
+    case K_GEMV: return tiles_gemv(p);
+    case K_PASS: return rup(tiles_pass(p), 8);
+    case K_PRED: return tiles_reduce(p);
+    case K_GRAM_SYM: return tiles_gram(p, false);
+    case K_GRAM_FULL: return tiles_gram(p, true);
+    case K_GRED: return (int)(((int64_t)p.rpad * p.rpad + 1023) / 1024);
+    case K_APPLY: return tiles_apply(p);
+    case K_BISECT: return tiles_bisect(p);
+    case K_INVIT: return tiles_invit(p);
+    case K_REBUILD: return tiles_rebuild(p);
+  }
+  return 0;
+}
+
+static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
+  auto add = [&](int kind, int arg, int when, int iter) { out.push_back(Stage{kind, arg, when, iter}); };
+  add(K_SETUP, 0, W_ALL, 0);
+  add(K_OMEGA, 0, W_ALL, 0);
+  if (max_iters > 0) {
+    for (int run = 0; run < 2; ++run) {
+      add(K_PINIT, run, W_ALPHA, 0);
+      for (int it = 0; it < max_iters; ++it) add(K_GEMV, 0, W_ALPHA_ITER, it);
+      add(K_GEMV, run + 1, W_ALPHA, 0);
+    }
+    add(K_ALPHA, 0, W_ALPHA, 0);
+  }
+  auto orth = [&](int when, int iter) {
+    add(K_PASS, 0, when, iter);
+    add(K_PRED, 0, when, iter);
+    add(K_GRAM_SYM, 0, when, iter);
+    add(K_GRED, 0, when, iter);
+    add(K_CHOL, 0, when, iter);
+    add(K_APPLY, 0, when, iter);
+    add(K_GRAM_SYM, 1, when, iter);
+    add(K_GRED, 1, when, iter);
+    add(K_CHOL, 1, when, iter);
+    add(K_APPLY, 1, when, iter);
+  };
+  orth(W_ALL, 0);
+  for (int it = 0; it < max_q; ++it) {
+    orth(W_POWER, it);
+    orth(W_POWER, it);
+  }
+  add(K_PASS, 0, W_ALL, 0);
+  add(K_PRED, 0, W_ALL, 0);
+  add(K_GRAM_FULL, 2, W_ALL, 0);
+  add(K_GRED, 2, W_ALL, 0);
+  add(K_TRIDIAG, 0, W_ALL, 0);
+  add(K_BISECT, 0, W_ALL, 0);
+  add(K_INVIT, 0, W_ALL, 0);
+  add(K_APPLY, 2, W_ALL, 0);
+  add(K_REBUILD, 0, W_ALL, 0);
+  add(K_FINAL, 0, W_ALL, 0);
+}
+
+void build_schedule(const Plan* const* plans, int count, Schedule& s) {
+  s.order.resize(count);
+  for (int i = 0; i < count; ++i) s.order[i] = i;
+  std::stable_sort(s.order.begin(), s.order.end(), [&](int a, int b) {
+    if (plans[a]->prec != plans[b]->prec) return plans[a]->prec < plans[b]->prec;
+    return plans[a]->ncb < plans[b]->ncb;
+  });
+  // groups of equal (prec, ncb), as ranges of the sorted order
+  s.groups.clear();
+  for (int i = 0; i < count;) {
+    int j = i;
+    while (j < count && plans[s.order[j]]->prec == plans[s.order[i]]->prec &&
+           plans[s.order[j]]->ncb == plans[s.order[i]]->ncb) ++j;
+    s.groups.push_back({i, j - i, plans[s.order[i]]->prec, plans[s.order[i]]->ncb});
+    i = j;
+  }
+  int max_iters = 0, max_q = 0;
+  for (int i = 0; i < count; ++i) {
+    if (plans[i]->alpha_mode == 1) max_iters = std::max(max_iters, plans[i]->d.alpha_iters);
+    max_q = std::max(max_q, plans[i]->d.q);
+  }
+  std::vector<Stage> stages;
+  stage_list(max_iters, max_q, stages);
+  // tile counts need only the sizes, so a Prob without pointers is enough here
+  std::vector<Prob> shape(count);
+  for (int i = 0; i < count; ++i) shape[i] = make_prob(*plans[s.order[i]], nullptr, nullptr, 0, nullptr, 0, nullptr);
+  s.launches.clear();
+  s.tdata.clear();
+  for (const Stage& st : stages) {
+    const bool grouped = (st.kind == K_PASS || st.kind == K_REBUILD);
+    const int ng = grouped ? (int)s.groups.size() : 1;
+    for (int g = 0; g < ng; ++g) {
+      const int first = grouped ? s.groups[g].first : 0;
+      const int cnt = grouped ? s.groups[g].count : count;
+      LaunchRec L;
+      L.kind = st.kind; L.arg = st.arg; L.first = first; L.count = cnt;
+      L.prec = grouped ? s.groups[g].prec : 0;
+      L.ncb = grouped ? s.groups[g].ncb : 0;
+      L.toff = (int)s.tdata.size();
+      int tot = 0;
+      s.tdata.push_back(0);
+      for (int i = 0; i < cnt; ++i) {
+        const Plan& pl = *plans[s.order[first + i]];
+        if (active_in(pl, st)) tot += stage_tiles(shape[first + i], st.kind);
+        s.tdata.push_back(tot);
+      }
+      L.grid = (unsigned)tot;
+      if (tot > 0) s.launches.push_back(L);
+      else s.tdata.resize(L.toff);
+    }
+  }
+  s.prob_bytes = al256((size_t)count * sizeof(Prob));
+  s.header_bytes = al256(s.prob_bytes + s.tdata.size() * sizeof(int));
+}
+
+// ------------------------------------------------------------------------------ upload ring
+// Small host-to-device uploads (descriptors, tile tables) go through pinned slots; each slot
+// is reused only after the event of its previous copy has completed.
+namespace {
+struct Slot { void* host = nullptr; size_t cap = 0; hipEvent_t ev = nullptr; bool used = false; };
+struct Ring {
+  std::mutex mu;
+  std::vector<Slot> slots;
+  size_t next = 0;
+};
+Ring& ring_for(int dev) {
+  static std::mutex gmu;
+  static std::vector<Ring*> rings;
+  std::lock_guard<std::mutex> g(gmu);
+  if ((int)rings.size() <= dev) rings.resize(dev + 1, nullptr);
+  if (!rings[dev]) { rings[dev] = new Ring(); rings[dev]->slots.resize(16); }
+  return *rings[dev];
+}
+}  // namespace
+
+psdproj_status upload(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PSDPROJ_E_DEVICE;
+  Ring& R = ring_for(dev);
+  std::lock_guard<std::mutex> g(R.mu);
+  Slot& s = R.slots[R.next];
+  R.next = (R.next + 1) % R.slots.size();
+  if (s.used && hipEventSynchronize(s.ev) != hipSuccess) return PSDPROJ_E_DEVICE;
+  if (s.cap < bytes) {
+    if (s.host) hipHostFree(s.host);
+    s.host = nullptr;
+    size_t cap = std::max(bytes, (size_t)65536);
+    if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) { s.cap = 0; return PSDPROJ_E_NOMEM; }
+    s.cap = cap;
+  }
+  if (!s.ev && hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) return PSDPROJ_E_DEVICE;
+  std::memcpy(s.host, src, bytes);
+  if (hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return PSDPROJ_E_DEVICE;
+  if (hipEventRecord(s.ev, stream) != hipSuccess) return PSDPROJ_E_DEVICE;
+  s.used = true;
+  return PSDPROJ_OK;
+}
+
+static void kernel_init_once() {
+  static std::mutex mu;
+  static std::vector<bool> done;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, false);
+  if (!done[dev]) { rebuild_init(); done[dev] = true; }
+}
+
+// Enqueue every launch of a schedule whose header (Prob array + tile tables) is at `hdr`.
+psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream) {
+  kernel_init_once();
+  const Prob* probs = (const Prob*)hdr;
+  const int* tdev = (const int*)(hdr + s.prob_bytes);
+  for (const LaunchRec& R : s.launches) {
+    Launch L{R.grid, probs + R.first, tdev + R.toff, R.count, stream};
+    switch (R.kind) {
+      case K_SETUP: launch_setup(L); break;
+      case K_OMEGA: launch_omega(L); break;
+      case K_PINIT: launch_power_init(L, R.arg); break;
+      case K_GEMV: launch_gemv(L, R.arg); break;
+      case K_ALPHA: launch_alpha(L); break;
+      case K_PASS: launch_pass(L, R.prec, R.ncb); break;
+      case K_PRED: launch_pass_reduce(L); break;
+      case K_GRAM_SYM: case K_GRAM_FULL: launch_gram(L, R.arg); break;
+      case K_GRED: launch_gram_reduce(L, R.arg); break;
+      case K_CHOL: launch_chol(L, R.arg); break;
+      case K_APPLY: launch_apply(L, R.arg); break;
+      case K_TRIDIAG: launch_tridiag(L); break;
+      case K_BISECT: launch_bisect(L); break;
+      case K_INVIT: launch_invit(L); break;
+      case K_REBUILD: launch_rebuild(L, R.prec); break;
+      case K_FINAL: launch_finalize(L); break;
+    }
+    if (hipGetLastError() != hipSuccess) return PSDPROJ_E_DEVICE;
+  }
+  return PSDPROJ_OK;
+}
+
+psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp) {
+  const int64_t n = pl.d.n;
+  if (!A || !P) return PSDPROJ_E_INVALID;
+  if (lda < n || ldp < n) return PSDPROJ_E_INVALID;
+  if (((uintptr_t)A & 15) || ((uintptr_t)P & 15)) return PSDPROJ_E_INVALID;
+  const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (uintptr_t)(((n - 1) * lda + n) * pl.es);
+  const uintptr_t p0 = (uintptr_t)P, p1 = p0 + (uintptr_t)(((n - 1) * ldp + n) * pl.es);
+  const bool overlap = (a0 < p1) && (p0 < a1);
+  if (overlap && !(A == P && lda == ldp)) return PSDPROJ_E_INVALID;
+  return PSDPROJ_OK;
+}
+
+psdproj_status run_group(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
+                         void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
+                         psdproj_result* results, hipStream_t stream) {
+  Schedule s;
+  build_schedule(plans, count, s);
+  size_t need = s.header_bytes;
+  for (int i = 0; i < count; ++i) need += plans[i]->region;
+  if (ws_bytes < need) return PSDPROJ_E_NOMEM;
+  std::vector<unsigned char> host(s.header_bytes, 0);
+  Prob* hp = (Prob*)host.data();
+  // regions follow the header in the caller's order
+  std::vector<size_t> roff(count);
+  size_t o = s.header_bytes;
+  for (int i = 0; i < count; ++i) { roff[i] = o; o += plans[i]->region; }
+  for (int k = 0; k < count; ++k) {
+    const int i = s.order[k];
+    hp[k] = make_prob(*plans[i], ws + roff[i], A[i], lda[i], P[i], ldp[i], results + i);
+  }
+  std::memcpy(host.data() + s.prob_bytes, s.tdata.data(), s.tdata.size() * sizeof(int));
+  psdproj_status st = upload(ws, host.data(), s.header_bytes, stream);
+  if (st != PSDPROJ_OK) return st;
+  return enqueue(s, ws, stream);
+}
+
+}  // namespace psd
+
+// ================================================================================ C ABI
+using namespace psd;
+
+extern "C" {
+
+psdproj_status psdproj_plan(const psdproj_desc* desc, psdproj_plan_t* out, size_t* workspace_bytes) {
+  if (!desc || !out) return PSDPROJ_E_INVALID;
+  *out = nullptr;
+  Plan* pl = new (std::nothrow) Plan();
+  if (!pl) return PSDPROJ_E_NOMEM;
+  psdproj_status st = make_plan(desc, *pl);
+  if (st != PSDPROJ_OK) { delete pl; return st; }
+  *out = (psdproj_plan_t)pl;
+  if (workspace_bytes) *workspace_bytes = pl->header_single + pl->region;
+  return PSDPROJ_OK;
+}
+
+void psdproj_plan_destroy(psdproj_plan_t plan) { delete (Plan*)plan; }
+
+psdproj_status psdproj_plan_layout(psdproj_plan_t plan, psdproj_layout* out) {
+  if (!plan || !out) return PSDPROJ_E_INVALID;
+  const Plan& pl = *(const Plan*)plan;
+  const size_t h = pl.header_single;
+  out->r = pl.r; out->r_pad = pl.rpad; out->panel_ld = pl.ld; out->split_k = pl.split;
+  out->panel_elem_bytes = pl.es;
+  out->omega = h + pl.o_zm;       // holds Omega until the first orthonormalisation
+  out->q_panel = h + pl.o_zm;     // holds Q after the last orthonormalisation
+  out->compressed = h + pl.o_C;
+  out->evals = h + pl.o_evals;
+  out->weights = h + pl.o_wts;
+  out->factor = h + pl.o_wf;
+  out->power_vec = h + pl.o_vec;
+  out->y_panel = h + pl.o_y;
+  out->gram = h + pl.o_G;
+  out->total = h + pl.region;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_run(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp, void* workspace,
+                           psdproj_result* result_dev, psdproj_stream_t stream) {
+  if (!plan || !workspace || !result_dev) return PSDPROJ_E_INVALID;
+  if ((uintptr_t)workspace & 255) return PSDPROJ_E_INVALID;
+  const Plan* pl = (const Plan*)plan;
+  psdproj_status st = check_operands(*pl, A, lda, P, ldp);
+  if (st != PSDPROJ_OK) return st;
+  return run_group(1, &pl, &A, &lda, &P, &ldp, (unsigned char*)workspace, pl->header_single + pl->region,
+                   result_dev, (hipStream_t)stream);
+}
+
+psdproj_status psdproj_batch_workspace(int32_t count, const psdproj_plan_t* plans, size_t* bytes) {
+  if (count < 1 || !plans || !bytes) return PSDPROJ_E_INVALID;
+  std::vector<const Plan*> pls(count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return PSDPROJ_E_INVALID;
+    pls[i] = (const Plan*)plans[i];
+  }
+  Schedule s;
+  build_schedule(pls.data(), count, s);
+  size_t need = s.header_bytes;
+  for (int i = 0; i < count; ++i) need += pls[i]->region;
+  *bytes = need;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_batch(int32_t count, const psdproj_plan_t* plans, const void* const* A, const int64_t* lda,
+                             void* const* P, const int64_t* ldp, void* workspace, size_t workspace_bytes,
+                             psdproj_result* results_dev, psdproj_stream_t stream) {
+  if (count < 1 || !plans || !A || !lda || !P || !ldp || !workspace || !results_dev) return PSDPROJ_E_INVALID;
+  if ((uintptr_t)workspace & 255) return PSDPROJ_E_INVALID;
+  std::vector<const Plan*> pls(count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return PSDPROJ_E_INVALID;
+    pls[i] = (const Plan*)plans[i];
+    psdproj_status st = check_operands(*pls[i], A[i], lda[i], P[i], ldp[i]);
+    if (st != PSDPROJ_OK) return st;
+  }
+  return run_group(count, pls.data(), A, lda, P, ldp, (unsigned char*)workspace, workspace_bytes, results_dev,
+                   (hipStream_t)stream);
+}
+
+psdproj_status psdproj_philox_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count, uint32_t* out_dev,
+                                    psdproj_stream_t stream) {
+  if (count < 0 || (count > 0 && !out_dev)) return PSDPROJ_E_INVALID;
+  launch_words(seed, stream_id, c0, count, out_dev, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_E_DEVICE;
+}
+
+psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count, double* out_dev,
+                                psdproj_stream_t stream) {
+  if (count < 0 || (count > 0 && !out_dev)) return PSDPROJ_E_INVALID;
+  launch_gauss(seed, stream_id, start, count, out_dev, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_E_DEVICE;
+}
+
+const char* psdproj_status_str(psdproj_status s) {
+  switch (s) {
+    case PSDPROJ_OK: return "ok";
+    case PSDPROJ_E_INVALID: return "invalid argument";
+    case PSDPROJ_E_ALPHA: return "estimated alpha is not positive and finite";
+    case PSDPROJ_E_NONFINITE: return "non-finite value in a Gram or compressed matrix";
+    case PSDPROJ_E_BREAKDOWN: return "orthonormalisation lost every direction";
+    case PSDPROJ_E_NOMEM: return "workspace too small or allocation failed";
+    case PSDPROJ_E_BUDGET: return "request exceeds the server HBM budget";
+    case PSDPROJ_E_DEVICE: return "HIP runtime error";
+    case PSDPROJ_E_PENDING: return "pending";
+    case PSDPROJ_E_TIMEOUT: return "timed out";
+  }
+  return "unknown status";
+}
+
+int32_t psdproj_abi_version(void) { return PSDPROJ_ABI_VERSION; }
+
+}  // extern "C"

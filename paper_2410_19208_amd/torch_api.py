@@ -1,0 +1,148 @@
+"""PyTorch plumbing around the C ABI: device buffers, streams and result read-back.
+
+Nothing here computes any step of the projection; it allocates the workspace and result
+buffers as torch tensors and passes their addresses to libpsdproj.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import (BF16X3, FP32, FP64, PLAIN, SCALED, Layout, Result, psdproj_batch, psdproj_batch_workspace,
+               psdproj_plan, psdproj_plan_destroy, psdproj_plan_layout, psdproj_run)
+
+__all__ = ["Projector", "BatchProjector", "stream_handle", "read_results", "PRECISIONS", "VARIANTS",
+           "storage_dtype"]
+
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+VARIANTS = {"plain": PLAIN, "scaled": SCALED}
+
+
+def storage_dtype(precision: int) -> torch.dtype:
+    return torch.float64 if precision == FP64 else torch.float32
+
+
+def stream_handle(stream: torch.cuda.Stream | None = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def read_results(buf: torch.Tensor, count: int = 1) -> list[Result]:
+    """Copy `count` device-written psdproj_result records to the host (synchronising)."""
+    raw = bytes(buf[: count * ctypes.sizeof(Result)].cpu().numpy().tobytes())
+    return [Result.from_buffer_copy(raw, i * ctypes.sizeof(Result)) for i in range(count)]
+
+
+class Projector:
+    """One plan with its own workspace and result buffers on `device`."""
+
+    def __init__(self, n, k, p, q=0, variant="plain", precision="bf16x3", seed=0, alpha=0.0,
+                 alpha_iters=10, device="cuda"):
+        self.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.n = int(n)
+        self.plan, self.ws_bytes = psdproj_plan(n, k, p, q, self.variant, self.precision, seed, alpha, alpha_iters)
+        self.layout: Layout = psdproj_plan_layout(self.plan)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.result_buf = torch.zeros(ctypes.sizeof(Result), dtype=torch.uint8, device=self.device)
+        self.dtype = storage_dtype(self.precision)
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan:
+            psdproj_plan_destroy(plan)
+            self.plan = None
+
+    def __call__(self, A: torch.Tensor, P: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if A.dtype != self.dtype or A.device != self.device or A.shape != (self.n, self.n):
+            raise ValueError(f"A must be a {self.n}x{self.n} {self.dtype} tensor on {self.device}")
+        if A.stride(1) != 1:
+            raise ValueError("A must be row-contiguous")
+        if P is None:
+            P = torch.empty_like(A)
+        psdproj_run(self.plan, A.data_ptr(), A.stride(0), P.data_ptr(), P.stride(0), self.workspace.data_ptr(),
+                    self.result_buf.data_ptr(), stream_handle(stream))
+        return P
+
+    def result(self) -> Result:
+        return read_results(self.result_buf, 1)[0]
+
+    # --- intermediates, for inspection after the stream has passed the run
+    def _panel(self, offset: int, cols: int) -> torch.Tensor:
+        L = self.layout
+        dt = torch.float64 if L.panel_elem_bytes == 8 else torch.float32
+        nbytes = cols * L.panel_ld * L.panel_elem_bytes
+        flat = self.workspace[offset: offset + nbytes].view(dt)
+        return flat.view(cols, L.panel_ld)[:, : self.n].t()
+
+    def q_panel(self) -> torch.Tensor:
+        return self._panel(self.layout.q_panel, self.layout.r)
+
+    def omega(self) -> torch.Tensor:
+        """Omega is only resident until the first orthonormalisation overwrites the panel."""
+        return self._panel(self.layout.omega, self.layout.r)
+
+    def y_panel(self) -> torch.Tensor:
+        return self._panel(self.layout.y_panel, self.layout.r)
+
+    def gram(self) -> torch.Tensor:
+        L = self.layout
+        flat = self.workspace[L.gram: L.gram + L.r_pad * L.r_pad * 8].view(torch.float64)
+        return flat.view(L.r_pad, L.r_pad)[: L.r, : L.r].t()
+
+    def compressed(self) -> torch.Tensor:
+        L = self.layout
+        flat = self.workspace[L.compressed: L.compressed + L.r_pad * L.r_pad * 8].view(torch.float64)
+        return flat.view(L.r_pad, L.r_pad)[: L.r, : L.r].t()
+
+    def evals(self) -> torch.Tensor:
+        L = self.layout
+        return self.workspace[L.evals: L.evals + L.r * 8].view(torch.float64)
+
+    def factor(self, r_plus: int) -> torch.Tensor:
+        """W (n x r_plus) with P = W W^T (row-major, row stride r_pad)."""
+        L = self.layout
+        dt = torch.float64 if L.panel_elem_bytes == 8 else torch.float32
+        rows = L.panel_ld
+        flat = self.workspace[L.factor: L.factor + rows * L.r_pad * L.panel_elem_bytes].view(dt)
+        return flat.view(rows, L.r_pad)[: self.n, :r_plus]
+
+
+class BatchProjector:
+    """A list of plans run through one psdproj_batch call."""
+
+    def __init__(self, specs, device="cuda"):
+        self.device = torch.device(device)
+        self.projectors = []
+        self.plans = []
+        for s in specs:
+            s = dict(s)
+            v = s.pop("variant", "plain")
+            pr = s.pop("precision", "bf16x3")
+            vv = VARIANTS[v] if isinstance(v, str) else int(v)
+            pp = PRECISIONS[pr] if isinstance(pr, str) else int(pr)
+            plan, _ = psdproj_plan(s["n"], s["k"], s["p"], s.get("q", 0), vv, pp, s.get("seed", 0),
+                                   s.get("alpha", 0.0), s.get("alpha_iters", 10))
+            self.plans.append(plan)
+            self.projectors.append((s["n"], storage_dtype(pp)))
+        self.ws_bytes = psdproj_batch_workspace(self.plans)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.result_buf = torch.zeros(len(self.plans) * ctypes.sizeof(Result), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        for p in getattr(self, "plans", []):
+            psdproj_plan_destroy(p)
+        self.plans = []
+
+    def __call__(self, As, Ps=None, stream=None):
+        if Ps is None:
+            Ps = [torch.empty_like(a) for a in As]
+        psdproj_batch(self.plans, [a.data_ptr() for a in As], [a.stride(0) for a in As],
+                      [p.data_ptr() for p in Ps], [p.stride(0) for p in Ps], self.workspace.data_ptr(),
+                      self.ws_bytes, self.result_buf.data_ptr(), stream_handle(stream))
+        return Ps
+
+    def results(self):
+        return read_results(self.result_buf, len(self.plans))

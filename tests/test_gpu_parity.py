@@ -1,0 +1,172 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import _gpu
+from _gpu import TOL, matrix, parity, run_gpu, run_oracle
+from oracle import philox, rnla
+
+pytestmark = pytest.mark.gpu
+
+
+def test_philox_words_bit_exact():
+    import torch
+    import paper_2410_19208_amd as pp
+    dev = _gpu.device()
+    for seed, stream, c0, cnt in [(0, 0, 0, 1000), (123456789, 1, 2**33 + 7, 4097), (2**63 + 5, 2, 99, 10)]:
+        out = torch.zeros(4 * cnt, dtype=torch.int32, device=dev)
+        pp.psdproj_philox_words(seed, stream, c0, cnt, out.data_ptr(), 0)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32).reshape(cnt, 4)
+        ref = philox.raw_words(seed, stream, np.arange(c0, c0 + cnt, dtype=np.uint64))
+        assert np.array_equal(got, ref)
+
+
+def test_gaussian_stream_matches():
+    import torch
+    import paper_2410_19208_amd as pp
+    dev = _gpu.device()
+    for seed, stream, start, cnt in [(0, 0, 0, 50001), (77, 1, 3, 1000), (5, 2, 2**35, 64)]:
+        out = torch.zeros(cnt, dtype=torch.float64, device=dev)
+        pp.psdproj_gaussian(seed, stream, start, cnt, out.data_ptr(), 0)
+        torch.cuda.synchronize()
+        ref = philox.gaussian(seed, stream, cnt, start)
+        assert np.max(np.abs(out.cpu().numpy() - ref)) < 1e-13
+
+
+def test_small_fp64_workload_stages():
+    """n = 512, k = 40, p = 10, q = 0, plain, FP64: Omega, Ritz values, r_plus and P."""
+    n, k, p = 512, 40, 10
+    A, lam, U = matrix("small", n, 1001)
+    proj, P, res = run_gpu(A, k, p, 0, "plain", "fp64", seed=0)
+    ref = run_oracle(A, k, p, 0, "plain", "fp64", seed=0)
+    assert res.status == 0
+    assert res.r_plus == ref.r_plus
+    ev = proj.evals().cpu().numpy()
+    assert np.max(np.abs(np.sort(ev) - ref.evals)) < 1e-12 * np.abs(ref.evals).max()
+    Q = proj.q_panel().cpu().numpy()
+    assert np.linalg.norm(Q @ Q.T - ref.Q @ ref.Q.T) < 1e-11
+    assert parity(P, ref, A) < TOL["fp64"]
+    assert np.array_equal(P, P.T)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("variant,alpha", [("plain", 0.0), ("scaled", 0.35), ("scaled", 0.0)])
+@pytest.mark.parametrize("q", [0, 1])
+def test_parity_ragged(prec, variant, alpha, q):
+    """n = 777 (ragged against every tile), k = 40, p = 12."""
+    n, k, p = 777, 40, 12
+    A, lam, U = matrix("medium", n, 5, n_pos=60)
+    proj, P, res = run_gpu(A, k, p, q, variant, prec, seed=3, alpha=alpha)
+    ref = run_oracle(A, k, p, q, variant, prec, seed=3, alpha=alpha)
+    assert res.status == 0
+    if variant == "scaled" and alpha == 0.0:
+        assert abs(res.alpha_used - ref.alpha) < 1e-10 * ref.alpha
+    err = parity(P, ref, A)
+    print(f"{prec} {variant} alpha={alpha} q={q}: parity {err:.3e} r+ {res.r_plus}/{ref.r_plus}")
+    assert err < TOL[prec]
+    assert np.array_equal(P, P.T)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_exact_recovery(prec):
+    """rank(A) <= k+p: the projection is A_+ (closed form) to working precision."""
+    n = 300
+    rng = np.random.default_rng(2)
+    lam = np.zeros(n)
+    lam[:12] = rng.uniform(0.2, 2, 12)
+    lam[12:24] = -rng.uniform(0.2, 2, 12)
+    A, _, U = matrix("spectrum", n, 9, lam=lam)
+    proj, P, res = run_gpu(A, 24, 8, 1, "plain", prec, seed=1)
+    Ap = (U * np.maximum(lam, 0)) @ U.T
+    err = np.linalg.norm(P - Ap) / np.linalg.norm(Ap)
+    assert err < {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 5e-5}[prec]
+
+
+@pytest.mark.parametrize("n,k,p", [(1, 1, 0), (2, 1, 1), (3, 1, 0), (17, 5, 3), (40, 30, 10), (129, 100, 29)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_edge_sizes(n, k, p, prec):
+    A, lam, U = matrix("spectrum", n, 4, lam=np.linspace(1.0, -1.0, n))
+    for variant, alpha in [("plain", 0.0), ("scaled", 1.2)]:
+        proj, P, res = run_gpu(A, k, p, 1, variant, prec, seed=2, alpha=alpha)
+        ref = run_oracle(A, k, p, 1, variant, prec, seed=2, alpha=alpha)
+        assert res.status == 0
+        assert parity(P, ref, A) < TOL[prec]
+
+
+def test_zero_matrix():
+    n = 64
+    A = np.zeros((n, n))
+    proj, P, res = run_gpu(A, 8, 4, 1, "plain", "fp32", seed=0)
+    assert res.status == 0 and res.r_plus == 0 and not P.any()
+    proj, P, res = run_gpu(A, 8, 4, 1, "scaled", "fp32", seed=0, alpha=0.0)
+    import paper_2410_19208_amd as pp
+    assert res.status == pp.E_ALPHA
+
+
+def test_nonfinite_input_is_reported():
+    import paper_2410_19208_amd as pp
+    A, _, _ = matrix("small", 100, 3, n_pos=5)
+    A[7, 9] = A[9, 7] = np.nan
+    proj, P, res = run_gpu(A, 8, 4, 0, "plain", "fp32", seed=0)
+    assert res.status == pp.E_NONFINITE
+
+
+def test_in_place_output_aliases_input():
+    import torch
+    from paper_2410_19208_amd.torch_api import Projector
+    dev = _gpu.device()
+    A, _, _ = matrix("small", 500, 8, n_pos=30)
+    A32 = A.astype(np.float32)
+    proj = Projector(500, 30, 10, 1, "scaled", "bf16x3", seed=4, device=dev)
+    At = _gpu.to_dev(A32, dev)
+    P_sep = proj(At).cpu().numpy()
+    At2 = _gpu.to_dev(A32, dev)
+    proj(At2, P=At2)
+    torch.cuda.synchronize()
+    assert np.array_equal(At2.cpu().numpy(), P_sep)
+
+
+def test_batch_equals_single_runs_bitwise():
+    import torch
+    from paper_2410_19208_amd.torch_api import BatchProjector, Projector
+    dev = _gpu.device()
+    specs = [dict(n=300, k=20, p=8, q=1, variant="plain", precision="bf16x3", seed=1),
+             dict(n=1000, k=60, p=10, q=0, variant="scaled", precision="bf16x3", seed=2),
+             dict(n=77, k=10, p=5, q=2, variant="scaled", precision="fp32", seed=3, alpha=0.5),
+             dict(n=512, k=40, p=10, q=0, variant="plain", precision="fp64", seed=0),
+             dict(n=650, k=20, p=8, q=1, variant="plain", precision="bf16x3", seed=5)]
+    As = []
+    for i, s in enumerate(specs):
+        A, _, _ = matrix("small", s["n"], 20 + i, n_pos=max(2, s["n"] // 10))
+        As.append(_gpu.to_dev(A.astype(_gpu.storage(s["precision"])), dev))
+    bp = BatchProjector(specs, device=dev)
+    Pb = bp(As)
+    torch.cuda.synchronize()
+    rb = bp.results()
+    for i, s in enumerate(specs):
+        s2 = dict(s)
+        proj = Projector(s2.pop("n"), s2.pop("k"), s2.pop("p"), device=dev, **s2)
+        P1 = proj(As[i])
+        torch.cuda.synchronize()
+        assert proj.result().status == 0 and rb[i].status == 0
+        assert proj.result().r_plus == rb[i].r_plus
+        assert torch.equal(P1, Pb[i]), f"batch member {i} differs from its single run"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("variant", ["plain", "scaled"])
+@pytest.mark.parametrize("q", [0, 1])
+def test_medium_workload(prec, variant, q):
+    """n = 4096, k = 100, p = 10 (spectrum 1/i head, uniform negative tail, Gaussian noise)."""
+    n, k, p = 4096, 100, 10
+    for seed in (0, 1):
+        A, lam, U = matrix("medium", n, seed, noise=1e-3 / np.sqrt(n))
+        proj, P, res = run_gpu(A, k, p, q, variant, prec, seed=seed)
+        ref = run_oracle(A, k, p, q, variant, prec, seed=seed)
+        assert res.status == 0
+        err = parity(P, ref, A)
+        print(f"medium {prec} {variant} q={q} seed={seed}: parity {err:.3e} r+ {res.r_plus}/{ref.r_plus}")
+        assert err < TOL[prec]
