@@ -175,6 +175,16 @@ psdproj_status psdproj_philox_words(uint64_t seed, uint32_t stream_id, uint64_t 
 psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count,
                                 double* out_dev, psdproj_stream_t stream);
 
+/* Kernel timing (tracing aid, off by default).  While enabled, every launch of the library
+ * is bracketed by HIP events recorded on the launch stream; psdproj_profile_read waits for
+ * them and returns the accumulated device time and launch count of one kernel kind
+ * (0 <= kind < psdproj_kernel_kinds(); psdproj_kernel_name gives the kernel's symbol stem). */
+psdproj_status psdproj_profile_enable(int32_t enable);
+psdproj_status psdproj_profile_reset(void);
+psdproj_status psdproj_profile_read(int32_t kind, double* total_ms, int64_t* launches);
+int32_t        psdproj_kernel_kinds(void);
+const char*    psdproj_kernel_name(int32_t kind);
+
 const char* psdproj_status_str(psdproj_status status);
 int32_t     psdproj_abi_version(void);
 

@@ -82,14 +82,47 @@ _SIGS = {
     "psdproj_server_destroy": (None, [_vp]),
     "psdproj_philox_words": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
     "psdproj_gaussian": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
+    "psdproj_profile_enable": (_i32, [_i32]),
+    "psdproj_profile_reset": (_i32, []),
+    "psdproj_profile_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
+    "psdproj_kernel_kinds": (_i32, []),
+    "psdproj_kernel_name": (ctypes.c_char_p, [_i32]),
     "psdproj_status_str": (ctypes.c_char_p, [_i32]),
     "psdproj_abi_version": (_i32, []),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
-    _f = getattr(lib, _name)
+    try:
+        _f = getattr(lib, _name)
+    except AttributeError as _e:
+        raise ImportError(f"{LIB_PATH} does not export {_name}: it is stale, rebuild it with "
+                          "`python paper_2410_19208_amd/build.py`") from _e
     _f.restype = _res
     _f.argtypes = _args
+
+
+def psdproj_profile_enable(enable: bool = True) -> None:
+    _check(lib.psdproj_profile_enable(1 if enable else 0), "psdproj_profile_enable")
+
+
+def psdproj_profile_reset() -> None:
+    _check(lib.psdproj_profile_reset(), "psdproj_profile_reset")
+
+
+def psdproj_profile_read(kind: int):
+    """(total device milliseconds, launches) of one kernel kind since the last reset."""
+    t = _dbl()
+    c = _i64()
+    _check(lib.psdproj_profile_read(kind, ctypes.byref(t), ctypes.byref(c)), "psdproj_profile_read")
+    return t.value, c.value
+
+
+def psdproj_kernel_kinds() -> int:
+    return lib.psdproj_kernel_kinds()
+
+
+def psdproj_kernel_name(kind: int) -> str:
+    return lib.psdproj_kernel_name(kind).decode()
 
 
 def psdproj_status_str(status: int) -> str:

@@ -1,6 +1,8 @@
 """Build libpsdproj.so (HIP kernels + host runtime + C ABI) for gfx950, in-tree.
 
-    python -m paper_2410_19208_amd.build
+    python paper_2410_19208_amd/build.py
+
+(run as a file: importing the package would load the library this script rebuilds)
 
 Every source under csrc/ is compiled by hipcc into _build/ and linked into
 paper_2410_19208_amd/libpsdproj.so.

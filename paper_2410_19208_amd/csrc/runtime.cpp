@@ -311,13 +311,60 @@ static void kernel_init_once() {
   if (!done[dev]) { rebuild_init(); done[dev] = true; }
 }
 
+// ------------------------------------------------------------------------------ kernel timing
+namespace {
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  struct Pending { int kind; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[K_NKINDS] = {};
+  int64_t count[K_NKINDS] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void resolve() {  // caller holds mu
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        total_ms[p.kind] += ms;
+        count[p.kind] += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+};
+Prof& prof() { static Prof P; return P; }
+}  // namespace
+
 // Enqueue every launch of a schedule whose header (Prob array + tile tables) is at `hdr`.
 psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream) {
   kernel_init_once();
   const Prob* probs = (const Prob*)hdr;
   const int* tdev = (const int*)(hdr + s.prob_bytes);
+  Prof& PR = prof();
+  std::unique_lock<std::mutex> plock(PR.mu, std::defer_lock);
+  bool timing = false;
+  {
+    std::lock_guard<std::mutex> g(PR.mu);
+    timing = PR.on;
+  }
   for (const LaunchRec& R : s.launches) {
     Launch L{R.grid, probs + R.first, tdev + R.toff, R.count, stream};
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (timing) {
+      plock.lock();
+      ea = PR.get();
+      eb = PR.get();
+      plock.unlock();
+      if (ea) hipEventRecord(ea, stream);
+    }
     switch (R.kind) {
       case K_SETUP: launch_setup(L); break;
       case K_OMEGA: launch_omega(L); break;
@@ -337,9 +384,20 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
       case K_FINAL: launch_finalize(L); break;
     }
     if (hipGetLastError() != hipSuccess) return PSDPROJ_E_DEVICE;
+    if (timing && ea && eb) {
+      hipEventRecord(eb, stream);
+      plock.lock();
+      PR.pending.push_back({R.kind, ea, eb});
+      plock.unlock();
+    }
   }
   return PSDPROJ_OK;
 }
+
+static const char* const KIND_NAMES[K_NKINDS] = {
+    "k_setup", "k_omega", "k_power_init", "k_gemv", "k_alpha", "k_pass", "k_pass_reduce", "k_gram",
+    "k_gram_full", "k_gram_reduce", "k_chol", "k_apply", "k_tridiag", "k_bisect", "k_invit", "k_rebuild",
+    "k_finalize"};
 
 psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp) {
   const int64_t n = pl.d.n;
@@ -490,5 +548,37 @@ const char* psdproj_status_str(psdproj_status s) {
 }
 
 int32_t psdproj_abi_version(void) { return PSDPROJ_ABI_VERSION; }
+
+psdproj_status psdproj_profile_enable(int32_t enable) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.on = enable != 0;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_profile_reset(void) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.resolve();
+  for (int k = 0; k < K_NKINDS; ++k) { P.total_ms[k] = 0.0; P.count[k] = 0; }
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_profile_read(int32_t kind, double* total_ms, int64_t* launches) {
+  if (kind < 0 || kind >= K_NKINDS || !total_ms || !launches) return PSDPROJ_E_INVALID;
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.resolve();
+  *total_ms = P.total_ms[kind];
+  *launches = P.count[kind];
+  return PSDPROJ_OK;
+}
+
+int32_t psdproj_kernel_kinds(void) { return K_NKINDS; }
+
+const char* psdproj_kernel_name(int32_t kind) {
+  if (kind < 0 || kind >= K_NKINDS) return "";
+  return KIND_NAMES[kind];
+}
 
 }  // extern "C"
