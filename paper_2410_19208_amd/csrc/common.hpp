@@ -94,4 +94,33 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Tile t of the upper triangle of an nb x nb grid of 16x16 tiles, enumerated row by row:
+// (0,0), (0,1), ..., (0,nb-1), (1,1), ...
+__device__ __forceinline__ void upper_tile(int t, int nb, int& I, int& J) {
+  int i = 0, rem = t;
+  while (rem >= nb - i) { rem -= nb - i; ++i; }
+  I = i;
+  J = i + rem;
+}
+
+// Register-resident symmetric r_pad x r_pad FP64 matrices (one workgroup of SYM_WAVES waves):
+// the upper-triangle 16x16 tiles are dealt round-robin to the waves (tile t -> wave t % 16,
+// slot t / 16); lane l of the owner holds row l%16, columns 4*(l/16) .. +3 of the tile.
+constexpr int SYM_WAVES = 16;
+constexpr int SYM_THREADS = SYM_WAVES * 64;
+constexpr int SYM_SLOTS = (PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2 / SYM_WAVES + 1;  // 9
+
+// Number of eigenvalues of T below x (Sturm sequence).
+__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int r, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  int c = q < 0.0;
+  for (int i = 1; i < r; ++i) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = (d[i] - x) - e2[i - 1] / q;
+    c += q < 0.0;
+  }
+  return c;
+}
+
 }  // namespace psd

@@ -15,140 +15,7 @@
 
 namespace psd {
 
-constexpr int TRI_THREADS = 256;
 
-// Number of eigenvalues of T below x (Sturm sequence).
-__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int r, double x,
-                                           double pivmin) {
-  double q = d[0] - x;
-  int c = q < 0.0;
-  for (int i = 1; i < r; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = (d[i] - x) - e2[i - 1] / q;
-    c += q < 0.0;
-  }
-  return c;
-}
-
-__global__ __launch_bounds__(TRI_THREADS) void k_tridiag(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                         int nprob) {
-  const int pi = find_prob(tstart, nprob, blockIdx.x);
-  const Prob& p = probs[pi];
-  const int r = p.r, rp = p.rpad;
-  double* __restrict__ H = p.H;
-  __shared__ double v[PSDPROJ_MAX_RANK], w[PSDPROJ_MAX_RANK], red[TRI_THREADS / WAVE];
-  __shared__ double s_tau, s_K;
-
-  for (int64_t e = threadIdx.x; e < (int64_t)rp * rp; e += TRI_THREADS) H[e] = p.C[e];
-  __syncthreads();
-
-  for (int j = 0; j + 2 < r; ++j) {
-    // x = H[j+1 .., j]; sigma = ||x[1:]||^2
-    double part = 0.0;
-    for (int i = j + 2 + threadIdx.x; i < r; i += TRI_THREADS) {
-      const double x = H[(int64_t)j * rp + i];
-      part += x * x;
-    }
-    part = wave_sum(part);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sigma = 0.0;
-      for (int wv = 0; wv < TRI_THREADS / WAVE; ++wv) sigma += red[wv];
-      const double alpha = H[(int64_t)j * rp + j + 1];
-      double tau = 0.0, beta = alpha;
-      if (sigma > 0.0) {
-        const double mu = sqrt(alpha * alpha + sigma);
-        beta = (alpha <= 0.0) ? mu : -mu;
-        tau = (beta - alpha) / beta;
-        s_K = 1.0 / (alpha - beta);  // scale of x[1:] into v
-      } else {
-        s_K = 0.0;
-      }
-      s_tau = tau;
-      p.te[j] = beta;
-      p.td[j] = H[(int64_t)j * rp + j];
-      p.tau[j] = tau;
-    }
-    __syncthreads();
-    const double tau = s_tau, sc = s_K;
-    for (int i = threadIdx.x; i < r; i += TRI_THREADS) {
-      double vi = 0.0;
-      if (i == j + 1) vi = 1.0;
-      else if (i > j + 1) vi = H[(int64_t)j * rp + i] * sc;
-      v[i] = vi;
-    }
-    __syncthreads();
-    // store v[j+2..] in column j below the subdiagonal (kept for the back-transformation)
-    for (int i = j + 2 + threadIdx.x; i < r; i += TRI_THREADS) H[(int64_t)j * rp + i] = v[i];
-    if (tau != 0.0) {
-      // p = tau * A2 v (A2 symmetric: row i = column i)
-      for (int i = j + 1 + threadIdx.x; i < r; i += TRI_THREADS) {
-        const double* col = H + (int64_t)i * rp;
-        double s = 0.0;
-        for (int k = j + 1; k < r; ++k) s += col[k] * v[k];
-        w[i] = tau * s;
-      }
-      __syncthreads();
-      // K = tau/2 * p^T v
-      double dp = 0.0;
-      for (int i = j + 1 + threadIdx.x; i < r; i += TRI_THREADS) dp += w[i] * v[i];
-      dp = wave_sum(dp);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dp;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int wv = 0; wv < TRI_THREADS / WAVE; ++wv) s += red[wv];
-        s_K = 0.5 * tau * s;
-      }
-      __syncthreads();
-      const double K = s_K;
-      for (int i = j + 1 + threadIdx.x; i < r; i += TRI_THREADS) w[i] = w[i] - K * v[i];
-      __syncthreads();
-      // A2 -= v w^T + w v^T
-      for (int c = j + 1 + threadIdx.x; c < r; c += TRI_THREADS) {
-        double* col = H + (int64_t)c * rp;
-        const double vc = v[c], wc = w[c];
-        for (int i = j + 1; i < r; ++i) col[i] -= v[i] * wc + w[i] * vc;
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (r >= 2) {
-      p.td[r - 2] = H[(int64_t)(r - 2) * rp + r - 2];
-      p.te[r - 2] = H[(int64_t)(r - 2) * rp + r - 1];
-      p.tau[r - 2] = 0.0;
-    }
-    p.td[r - 1] = H[(int64_t)(r - 1) * rp + r - 1];
-    if (r >= 1) p.tau[r - 1] = 0.0;
-    // Gershgorin interval, norm, pivmin, squared off-diagonals
-    double gl = 1e308, gu = -1e308, emax2 = 0.0;
-    for (int i = 0; i < r; ++i) {
-      const double el = (i > 0) ? fabs(p.te[i - 1]) : 0.0;
-      const double er = (i + 1 < r) ? fabs(p.te[i]) : 0.0;
-      gl = fmin(gl, p.td[i] - el - er);
-      gu = fmax(gu, p.td[i] + el + er);
-      if (i + 1 < r) emax2 = fmax(emax2, p.te[i] * p.te[i]);
-    }
-    const double tnorm = fmax(fabs(gl), fabs(gu));
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-    const double slack = 2.0 * 2.220446049250313e-16 * tnorm + 2.0 * pivmin;
-    gl -= slack + 1e-300;
-    gu += slack + 1e-300;
-    for (int i = 0; i + 1 < r; ++i) p.evals[PSDPROJ_MAX_RANK + i] = p.te[i] * p.te[i];  // e^2 scratch
-    p.scal[S_TNORM] = tnorm;
-    p.scal[8] = gl;
-    p.scal[9] = gu;
-    p.scal[10] = pivmin;
-    const double thr = (p.variant == PSDPROJ_SCALED) ? 1.0 : 0.0;
-    p.scal[S_THRESH] = thr;
-    int nu = isfinite(tnorm) ? sturm_count(p.td, p.evals + PSDPROJ_MAX_RANK, r, thr, pivmin) : r;
-    if (nu < 0) nu = 0;
-    if (nu > r) nu = r;
-    p.iscal[I_NU] = nu;
-  }
-}
 
 // One wave per eigenvalue index j (ascending); lane l tests x_l = lo + (hi - lo)(l+1)/65.
 __global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, const int* __restrict__ tstart,
@@ -329,9 +196,6 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
 int tiles_bisect(const Prob& p) { return (p.r + 3) / 4; }
 int tiles_invit(const Prob& p) { return p.r; }
 
-void launch_tridiag(const Launch& L) {
-  hipLaunchKernelGGL(k_tridiag, dim3(L.grid), dim3(TRI_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
-}
 void launch_bisect(const Launch& L) {
   hipLaunchKernelGGL(k_bisect, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob);
 }

@@ -44,6 +44,7 @@ void launch_gram_reduce(const Launch& L, int mode);
 // Orthonormalisation factors (one block per problem) and panel products.
 void launch_chol(const Launch& L, int round);
 void launch_apply(const Launch& L, int round);
+void apply_init();
 
 // Eigensolver of the compressed matrix and the rebuild.
 void launch_tridiag(const Launch& L);

@@ -308,7 +308,7 @@ static void kernel_init_once() {
   hipGetDevice(&dev);
   std::lock_guard<std::mutex> g(mu);
   if ((int)done.size() <= dev) done.resize(dev + 1, false);
-  if (!done[dev]) { rebuild_init(); done[dev] = true; }
+  if (!done[dev]) { rebuild_init(); apply_init(); done[dev] = true; }
 }
 
 // ------------------------------------------------------------------------------ kernel timing
