@@ -88,6 +88,10 @@ __device__ __forceinline__ void set_status(const Prob& p, int st) {
   atomicCAS(&p.iscal[I_STATUS], 0, st);
 }
 
+// Wave index within the workgroup as a wave-uniform (scalar) value, so that branches and
+// addresses derived from it stay scalar.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -104,9 +108,9 @@ __device__ __forceinline__ void upper_tile(int t, int nb, int& I, int& J) {
 }
 
 // Register-resident symmetric r_pad x r_pad FP64 matrices (one workgroup of SYM_WAVES waves):
-// the upper-triangle 16x16 tiles are dealt round-robin to the waves (tile t -> wave t % 16,
-// slot t / 16); lane l of the owner holds row l%16, columns 4*(l/16) .. +3 of the tile.
-constexpr int SYM_WAVES = 16;
+// the upper-triangle 16x16 tiles are dealt round-robin to the waves (tile t -> wave t % SYM_WAVES,
+// slot t / SYM_WAVES); lane l of the owner holds row l%16, columns 4*(l/16) .. +3 of the tile.
+constexpr int SYM_WAVES = 8;
 constexpr int SYM_THREADS = SYM_WAVES * 64;
 constexpr int SYM_SLOTS = (PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2 / SYM_WAVES + 1;  // 9
 

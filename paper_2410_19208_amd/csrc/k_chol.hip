@@ -2,14 +2,17 @@
 //   G = Y^T Y, G = R^T R, Q1 = Y R^-1; then once more on Q1.
 // The range of Q equals the range of Y for any invertible R, which is all the method uses.
 //
-// k_chol (one workgroup of 16 waves per problem): right-looking Cholesky with the upper
-// triangle of G held in registers as 16x16 FP64 tiles (tile t of the upper triangle lives in
-// wave t mod 16; lane l holds row l%16, columns 4*(l/16)..+3 of it).  Step j broadcasts the
-// pivot row through LDS (double-buffered, one barrier per step) and every lane applies the
-// rank-1 update to its own elements.  A column whose Schur pivot is below tol * (its Gram
-// diagonal) lies in the span of the previous columns to working precision; it is dropped
-// (zero row of R, zero column of Q), which leaves the range unchanged.  R goes to H, and the
-// inverses of R's 16x16 diagonal blocks to the diagonal blocks of F.
+// k_chol (one workgroup of 16 waves per problem): blocked right-looking Cholesky on
+// 16x16 FP64 tiles.  The upper-triangle tiles of G live in registers (tile t in wave t mod 16)
+// in the result layout of v_mfma_f64_16x16x4f64 (lane l holds rows 4v + l/16,
+// column l%16), which is also that instruction's B-operand layout.  For each block column J:
+//   A. the owner of tile (J,J) factors it in LDS (16 scalar steps) and inverts R_JJ;
+//   B. the panel tiles become R_JK = R_JJ^-T W_JK (MFMA; B operand straight from registers);
+//   C. the trailing tiles take W_KL -= R_JK^T R_JL (MFMA; operands from the panel in LDS).
+// A column whose Schur pivot is below tol * (its Gram diagonal) lies in the span of the
+// previous columns to working precision; it is dropped (zero row of R and zero column of
+// R_JJ^-1, hence a zero column of Q), which leaves the range unchanged.  R goes to H, the
+// inverses of the diagonal blocks to the diagonal blocks of F.
 //
 // k_apply, rounds 0/1: Q = Y R^-1 by blocked forward substitution on v_mfma_f64_16x16x4f64,
 //   Q_J = (Y_J - sum_{I<J} Q_I R_IJ) R_JJ^-1   (16-column blocks; each wave owns 16 rows).
@@ -19,116 +22,171 @@
 
 namespace psd {
 
-constexpr int CH_WAVES = SYM_WAVES;
-constexpr int CH_THREADS = SYM_THREADS;
-constexpr int CH_SLOTS = SYM_SLOTS;
+constexpr int CH_WAVES = 16;
+constexpr int CH_THREADS = CH_WAVES * WAVE;
+constexpr int NBMAX = PSDPROJ_MAX_RANK / 16;
 
+// NS register slots per wave: 7 cover r_pad <= 224 (105 tiles), 9 cover r_pad = 256 (136).
+template <int NS>
 __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                      int nprob, int round) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int r = p.r, rp = p.rpad, nb = rp / 16, nt = nb * (nb + 1) / 2;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, kg = lane >> 4;
+  const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, li = lane & 15, kg = lane >> 4;
   const double* __restrict__ G = p.G;
   double* __restrict__ H = p.H;
   double* __restrict__ F = p.F;
-  __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];
+  __shared__ double panel[NBMAX][16][17];   // R_JK of the current block row, row-major
+  __shared__ double dsm[16][17];            // diagonal tile being factored
+  __shared__ double dinv[16][17];           // R_JJ^-1
   __shared__ double g0[PSDPROJ_MAX_RANK];
   __shared__ int dflag[PSDPROJ_MAX_RANK];
   const double tol = (p.prec == F64) ? 1e-26 : 1e-13;
 
   for (int j = tid; j < rp; j += CH_THREADS) g0[j] = (j < r) ? G[(int64_t)j * rp + j] : 0.0;
 
-  double reg[CH_SLOTS][4];
-  int tI[CH_SLOTS], tJ[CH_SLOTS];
+  f64x4 reg[NS];
+  int tI[NS], tJ[NS];
 #pragma unroll
-  for (int s = 0; s < CH_SLOTS; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int t = wave + s * CH_WAVES;
-    int I = nb, J = nb;  // inactive slot: beyond every index
+    int I = nb, J = nb;  // inactive slot
     if (t < nt) upper_tile(t, nb, I, J);
     tI[s] = I;
     tJ[s] = J;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int a = 16 * I + li, b = 16 * J + 4 * kg + q;
-      reg[s][q] = (t < nt) ? G[(int64_t)b * rp + a] : 0.0;
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * I + 4 * v + kg, b = 16 * J + li;
+      reg[s][v] = (t < nt) ? G[(int64_t)b * rp + a] : 0.0;
     }
   }
   __syncthreads();
 
-  int ndrop = 0;
-  for (int j = 0; j < r; ++j) {
-    double* buf = rowbuf[j & 1];
-    const int jb = j >> 4, ji = j & 15;
-    // owners publish row j (columns b >= j) of the current Schur complement
+  for (int J = 0; J < nb; ++J) {
+    // ---- A: factor the diagonal tile (owner wave), R_JJ and R_JJ^-1 into LDS
+    const int tdiag = J * nb - J * (J - 1) / 2;
+    if (wave == tdiag % CH_WAVES) {
+      const int sd = tdiag / CH_WAVES;
+      f64x4 dt = {0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < CH_SLOTS; ++s) {
-      if (tI[s] == jb && li == ji) {
+      for (int s = 0; s < NS; ++s)
+        if (s == sd) dt = reg[s];
+      {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int b = 16 * tJ[s] + 4 * kg + q;
-          if (b >= j) buf[b] = reg[s][q];
+        for (int v = 0; v < 4; ++v) dsm[4 * v + kg][li] = dt[v];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int jj = 0; jj < 16; ++jj) {
+          const int j = 16 * J + jj;
+          const double d = dsm[jj][jj], gj = g0[j];
+          const bool dr = !(gj > 0.0) || !(d > tol * gj) || !isfinite(d);
+          const double piv = dr ? 0.0 : sqrt(d);
+          const double ip = dr ? 0.0 : 1.0 / piv;
+          // lanes 0..15 hold the row-jj values of columns c = lane
+          double rowv = 0.0;
+          if (lane < 16) rowv = (lane > jj) ? dsm[jj][lane] * ip : 0.0;
+          __builtin_amdgcn_wave_barrier();
+          // trailing update of the tile: element (a, c), a, c > jj; 4 elements per lane
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int a = 4 * e + kg, c = li;
+            const double ua = __shfl(rowv, a, 64), uc = __shfl(rowv, c, 64);
+            if (a > jj && c > jj) dsm[a][c] -= ua * uc;
+          }
+          if (lane < 16) {
+            if (lane > jj) dsm[jj][lane] = rowv;
+            else if (lane == jj) dsm[jj][jj] = dr ? 1.0 : piv;
+          }
+          if (lane == 0) dflag[j] = dr;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
+        // R_JJ^-1: lane c < 16 solves R_JJ x = e_c by back substitution
+        if (lane < 16) {
+          const int c = lane;
+          for (int i = 15; i >= 0; --i) {
+            double acc = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k <= c; ++k) acc -= dsm[i][k] * dinv[k][c];
+            dinv[i][c] = (i > c || dflag[16 * J + i]) ? 0.0 : acc / dsm[i][i];
+          }
+        }
+        // R_JJ (upper, zero below) back into the owner's registers
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 4 * v + kg, c = li;
+          dt[v] = (a <= c) ? dsm[a][c] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (s == sd) reg[s] = dt;
       }
     }
     __syncthreads();
-    const double d = buf[j], gj = g0[j];
-    const bool dr = !(gj > 0.0) || !(d > tol * gj) || !isfinite(d);
-    const double piv = dr ? 0.0 : sqrt(d);
-    const double ip = dr ? 0.0 : 1.0 / piv;
-    ndrop += dr;
-    if (tid == 0) dflag[j] = dr;
+    if (wave == 0) {
 #pragma unroll
-    for (int s = 0; s < CH_SLOTS; ++s) {
-      if (tJ[s] >= nb || tJ[s] < jb) continue;       // inactive, or entirely left of column j
-      const int a = 16 * tI[s] + li;
-      if (a < j) continue;                            // rows of R already final
-      const double ua = buf[a] * ip;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int b = 16 * tJ[s] + 4 * kg + q;
-        if (a == j) {
-          if (b > j) reg[s][q] = buf[b] * ip;
-          else if (b == j) reg[s][q] = dr ? 1.0 : piv;
-        } else if (b > j) {
-          reg[s][q] -= ua * (buf[b] * ip);
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int a = 4 * e + kg, c = li;
+        F[(int64_t)(16 * J + c) * rp + 16 * J + a] = dinv[a][c];
       }
     }
-  }
-  for (int j = r + tid; j < rp; j += CH_THREADS) dflag[j] = 1;
-  // R (upper triangle, zero-padded) to H
+    // Per-lane LDS offset (row kg, column li of a 16x17 tile), re-materialised every block so
+    // that per-slot addresses are not hoisted out of the loop (they would occupy registers).
+    int lofs = kg * 17 + li;
+    __asm__ volatile("" : "+v"(lofs));
+    const double* pan = &panel[0][0][0];
+    const double* dv = &dinv[0][0];
+    // ---- B: panel tiles R_JK = R_JJ^-T W_JK for K > J
 #pragma unroll
-  for (int s = 0; s < CH_SLOTS; ++s) {
+    for (int s = 0; s < NS; ++s) {
+      if (tI[s] != J || tJ[s] >= nb || tJ[s] == J) continue;
+      f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double a = dv[kk * 68 + lofs];   // (R_JJ^-T)[li][4kk+kg]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, reg[s][kk], acc, 0, 0, 0);
+      }
+      reg[s] = acc;
+      const int K = tJ[s];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) panel[K][4 * v + kg][li] = acc[v];
+    }
+    __syncthreads();
+    // ---- C: trailing tiles W_KL -= R_JK^T R_JL, J < K <= L
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (tI[s] <= J || tJ[s] >= nb) continue;
+      const int K = tI[s], L = tJ[s];
+      f64x4 acc = reg[s];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double a = pan[K * 272 + kk * 68 + lofs];   // (R_JK^T)[li][4kk+kg]
+        const double b = pan[L * 272 + kk * 68 + lofs];   // R_JL[4kk+kg][li]
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, b, acc, 0, 0, 0);
+      }
+      reg[s] = acc;
+    }
+    // the next block's step A reads only its owner's registers; the panel is rewritten after
+    // the next barrier
+  }
+  // R (upper-triangle tiles, now all final in registers) to H
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
     if (tJ[s] >= nb) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int a = 16 * tI[s] + li, b = 16 * tJ[s] + 4 * kg + q;
-      if (a <= b) H[(int64_t)b * rp + a] = (a < r && b < r) ? reg[s][q] : ((a == b) ? 1.0 : 0.0);
-      else H[(int64_t)b * rp + a] = 0.0;
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * tI[s] + 4 * v + kg, b = 16 * tJ[s] + li;
+      H[(int64_t)b * rp + a] = reg[s][v];
     }
   }
   __syncthreads();
-  // inverses of the 16x16 diagonal blocks of R: wave I, lane c < 16 solves R_II x = e_c
-  if (wave < nb && lane < 16) {
-    const int I = wave, c = lane, base = 16 * I;
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = 0.0;
-#pragma unroll
-    for (int i = 15; i >= 0; --i) {
-      if (i > c) continue;
-      const int gi = base + i;
-      double s = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = i + 1; k < 16; ++k)
-        if (k <= c) s -= H[(int64_t)(base + k) * rp + gi] * x[k];
-      x[i] = dflag[gi] ? 0.0 : s / H[(int64_t)gi * rp + gi];
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) F[(int64_t)(base + c) * rp + base + i] = x[i];
+  if (tid == 0) {
+    int ndrop = 0;
+    for (int j = 0; j < r; ++j) ndrop += dflag[j];
+    p.iscal[I_NDROP] = ndrop;
   }
-  if (tid == 0) p.iscal[I_NDROP] = ndrop;
   (void)round;
 }
 
@@ -137,9 +195,9 @@ constexpr int AP_WAVES = 4;
 constexpr int AP_THREADS = AP_WAVES * WAVE;
 
 template <typename T>
-__device__ void apply_tri(const Prob& p, int round, int tile, double* Qs) {
+__device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, double* Qs) {
   const int rp = p.rpad, nb = rp / 16, ld = p.ld, qld = rp + 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
+  const int wave = wave_id(), lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
   const int rowbase = tile * APPLY_ROWS + wave * 16;
   const T* __restrict__ in = (const T*)((round == 0) ? p.y : p.q1);
   T* __restrict__ out = (T*)((round == 0) ? p.q1 : p.zm);
@@ -190,9 +248,9 @@ __device__ void apply_tri(const Prob& p, int round, int tile, double* Qs) {
 
 // W = Q F, F = V_keep diag(sqrt(w)) (columns >= r_plus are zero); row-major output.
 template <typename T>
-__device__ void apply_factor(const Prob& p, int tile) {
+__device__ __forceinline__ void apply_factor(const Prob& p, int tile) {
   const int rp = p.rpad, nb = rp / 16, ld = p.ld, kw = p.rwpad;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
+  const int wave = wave_id(), lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
   const int rowbase = tile * APPLY_ROWS + wave * 16;
   const int rplus = min(max(p.iscal[I_RPLUS], 0), rp);
   const T* __restrict__ Q = (const T*)p.zm;
@@ -255,7 +313,10 @@ void apply_init() {
 }
 
 void launch_chol(const Launch& L, int round) {
-  hipLaunchKernelGGL(k_chol, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
+  if (L.maxnb <= 14)
+    hipLaunchKernelGGL(k_chol<7>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
+  else
+    hipLaunchKernelGGL(k_chol<9>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
 }
 void launch_apply(const Launch& L, int round) {
   hipLaunchKernelGGL(k_apply, dim3(L.grid), dim3(AP_THREADS), apply_smem(), L.stream, L.probs, L.tstart, L.nprob,

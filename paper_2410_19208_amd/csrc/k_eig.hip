@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, 
                                                 int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
-  const int j = (blockIdx.x - tstart[pi]) * 4 + (threadIdx.x >> 6);
+  const int j = (blockIdx.x - tstart[pi]) * 4 + wave_id();
   const int lane = threadIdx.x & 63;
   const int r = p.r;
   if (j >= r) return;

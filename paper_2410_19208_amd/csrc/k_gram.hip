@@ -41,7 +41,7 @@ __device__ void gram_tile(const Prob& p, int mode, int tile, int chunk) {
   gram_operands(p, mode, Xv, Yv);
   const T* X = (const T*)Xv;
   const T* Y = (const T*)Yv;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int li = lane & 15, kg = lane >> 4;
   const int ci = ti * GRAM_TILE + (wave >> 1) * 16 + li;   // X column (row of the result)
   const int cj = tj * GRAM_TILE + (wave & 1) * 16 + li;    // Y column (column of the result)

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict
   const int n = p.n, ld = p.ld;
   const int kbeg = s * p.kchunk;
   const int kend = min(n, kbeg + p.kchunk);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int lrow = lane & 15, kg = lane >> 4;
   const TA* __restrict__ A = (const TA*)p.A;
   const int64_t lda = p.lda;

@@ -24,7 +24,7 @@ __device__ void gemv_block(const Prob& p, int t, int last) {
   const double shift = p.scal[S_SHIFT];
   const T* __restrict__ A = (const T*)p.A;
   const int64_t lda = p.lda;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int row0 = t * GEMV_ROWS + wave * ROWS_PER_WAVE;
   __shared__ double red[4];
 

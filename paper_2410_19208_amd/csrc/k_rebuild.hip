@@ -41,7 +41,7 @@ __device__ void rebuild_tile(const Prob& p, int t) {
   tile_ij(t, I, J);
   const int n = p.n;
   const int I0 = I * TS, J0 = J * TS;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
   const int l16 = lane & 15, kg = lane >> 4;
   const int rplus = min(max(p.iscal[I_RPLUS], 0), p.rpad);
   const int kw = p.rwpad;

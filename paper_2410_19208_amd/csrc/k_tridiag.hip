@@ -17,21 +17,22 @@
 
 namespace psd {
 
+template <int NS>   // register slots per wave (14: r_pad <= 224, 17: r_pad = 256)
 __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                          int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int r = p.r, rp = p.rpad, nb = rp / 16, nt = nb * (nb + 1) / 2;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, kg = lane >> 4;
+  const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, li = lane & 15, kg = lane >> 4;
   __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];
   __shared__ double rpart[(PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2][16];
   __shared__ double cpart[(PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2][16];
   __shared__ double pvec[PSDPROJ_MAX_RANK];
 
-  double reg[SYM_SLOTS][4];
-  int tI[SYM_SLOTS], tJ[SYM_SLOTS];
+  double reg[NS][4];
+  int tI[NS], tJ[NS];
 #pragma unroll
-  for (int s = 0; s < SYM_SLOTS; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int t = wave + s * SYM_WAVES;
     int I = nb, J = nb;
     if (t < nt) upper_tile(t, nb, I, J);
@@ -47,15 +48,13 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
   for (int j = 0; j + 2 < r; ++j) {
     double* buf = rowbuf[j & 1];
     const int jb = j >> 4, ji = j & 15;
-    // 1. publish row j (columns >= j)
+    // 1. publish row j (the 16-column strips of row block jb; entries left of j are not read)
 #pragma unroll
-    for (int s = 0; s < SYM_SLOTS; ++s) {
-      if (tI[s] == jb && li == ji) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int b = 16 * tJ[s] + 4 * kg + q;
-          if (b >= j) buf[b] = reg[s][q];
-        }
+    for (int s = 0; s < NS; ++s) {
+      if (tI[s] == jb && tJ[s] < nb && li == ji) {
+        double* dst = buf + 16 * tJ[s] + 4 * kg;
+        *(double2*)dst = double2{reg[s][0], reg[s][1]};
+        *(double2*)(dst + 2) = double2{reg[s][2], reg[s][3]};
       }
     }
     __syncthreads();
@@ -81,17 +80,23 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
       // v_i: 0 (i <= j), 1 (i = j+1), buf[i] * sc (i >= j+2)
       // 3a. per-tile partial sums of C2 v (rows) and of C2^T v over the tile's rows (columns)
 #pragma unroll
-      for (int s = 0; s < SYM_SLOTS; ++s) {
-        if (tJ[s] >= nb || 16 * tJ[s] + 15 <= j) continue;   // no trailing columns in this tile
+      for (int s = 0; s < NS; ++s) {
+        if (tJ[s] >= nb || 16 * tJ[s] + 15 <= j) continue;   // (uniform) no trailing columns here
         const int t = wave + s * SYM_WAVES;
         const int a = 16 * tI[s] + li;
+        const int b0 = 16 * tJ[s] + 4 * kg;
+        const double2 x01 = *(const double2*)(buf + b0);
+        const double2 x23 = *(const double2*)(buf + b0 + 2);
+        const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
+        // v restricted to the trailing block; padding (>= r) is zero in buf and in the registers
         const double va = (a > j + 1) ? buf[a] * sc : (a == j + 1 ? 1.0 : 0.0);
+        const double ma = (a > j) ? 1.0 : 0.0;
         double rs = 0.0, cs[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int b = 16 * tJ[s] + 4 * kg + q;
-          const double vb = (b > j + 1) ? buf[b] * sc : (b == j + 1 ? 1.0 : 0.0);
-          const double x = (a > j && b > j && a < r && b < r) ? reg[s][q] : 0.0;
+          const int b = b0 + q;
+          const double vb = (b > j + 1) ? xb[q] * sc : (b == j + 1 ? 1.0 : 0.0);
+          const double x = (b > j) ? reg[s][q] * ma : 0.0;
           rs += x * vb;
           cs[q] = x * va;
         }
@@ -141,18 +146,24 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
       const double K = 0.5 * tau * wave_sum(dp);
       // 4. C2 -= v w^T + w v^T, w = p - K v
 #pragma unroll
-      for (int s = 0; s < SYM_SLOTS; ++s) {
+      for (int s = 0; s < NS; ++s) {
         if (tJ[s] >= nb || 16 * tJ[s] + 15 <= j) continue;
         const int a = 16 * tI[s] + li;
-        if (a <= j || a >= r) continue;
-        const double va = (a > j + 1) ? buf[a] * sc : 1.0;
-        const double wa = pvec[a] - K * va;
+        const int b0 = 16 * tJ[s] + 4 * kg;
+        const double2 x01 = *(const double2*)(buf + b0);
+        const double2 x23 = *(const double2*)(buf + b0 + 2);
+        const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
+        const double2 p01 = *(const double2*)(pvec + b0);
+        const double2 p23 = *(const double2*)(pvec + b0 + 2);
+        const double pb[4] = {p01.x, p01.y, p23.x, p23.y};
+        // rows/columns outside the trailing block get zero v and w (no update there)
+        const double va = (a > j + 1) ? buf[a] * sc : (a == j + 1 ? 1.0 : 0.0);
+        const double wa = (a > j) ? pvec[a] - K * va : 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int b = 16 * tJ[s] + 4 * kg + q;
-          if (b <= j || b >= r) continue;
-          const double vb = (b > j + 1) ? buf[b] * sc : 1.0;
-          const double wb = pvec[b] - K * vb;
+          const int b = b0 + q;
+          const double vb = (b > j + 1) ? xb[q] * sc : (b == j + 1 ? 1.0 : 0.0);
+          const double wb = (b > j) ? pb[q] - K * vb : 0.0;
           reg[s][q] -= va * wb + wa * vb;
         }
       }
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
   if (r >= 2) {
     const int j = r - 2;
 #pragma unroll
-    for (int s = 0; s < SYM_SLOTS; ++s) {
+    for (int s = 0; s < NS; ++s) {
       if (tI[s] >= nb) continue;
       const int a = 16 * tI[s] + li;
 #pragma unroll
@@ -177,7 +188,7 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < SYM_SLOTS; ++s)
+    for (int s = 0; s < NS; ++s)
       if (tI[s] == 0 && tJ[s] == 0 && li == 0 && kg == 0) p.td[0] = reg[s][0];
   }
   if (tid == 0) {
@@ -215,7 +226,10 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
 }
 
 void launch_tridiag(const Launch& L) {
-  hipLaunchKernelGGL(k_tridiag, dim3(L.grid), dim3(SYM_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+  if (L.maxnb <= 14)
+    hipLaunchKernelGGL(k_tridiag<14>, dim3(L.grid), dim3(SYM_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+  else
+    hipLaunchKernelGGL(k_tridiag<17>, dim3(L.grid), dim3(SYM_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
 }
 
 }  // namespace psd

@@ -11,6 +11,7 @@ struct Launch {
   const int* tstart;      // device array, nprob + 1 entries
   int nprob;
   hipStream_t stream;
+  int maxnb;              // largest r_pad / 16 among the launch's problems
 };
 
 // Tile counts per problem, shared by host planning and the kernels' tile decoding.

@@ -243,10 +243,14 @@ void build_schedule(const Plan* const* plans, int count, Schedule& s) {
       L.ncb = grouped ? s.groups[g].ncb : 0;
       L.toff = (int)s.tdata.size();
       int tot = 0;
+      L.maxnb = 1;
       s.tdata.push_back(0);
       for (int i = 0; i < cnt; ++i) {
         const Plan& pl = *plans[s.order[first + i]];
-        if (active_in(pl, st)) tot += stage_tiles(shape[first + i], st.kind);
+        if (active_in(pl, st)) {
+          tot += stage_tiles(shape[first + i], st.kind);
+          L.maxnb = std::max(L.maxnb, pl.rpad / 16);
+        }
         s.tdata.push_back(tot);
       }
       L.grid = (unsigned)tot;
@@ -356,7 +360,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
     timing = PR.on;
   }
   for (const LaunchRec& R : s.launches) {
-    Launch L{R.grid, probs + R.first, tdev + R.toff, R.count, stream};
+    Launch L{R.grid, probs + R.first, tdev + R.toff, R.count, stream, R.maxnb};
     hipEvent_t ea = nullptr, eb = nullptr;
     if (timing) {
       plock.lock();

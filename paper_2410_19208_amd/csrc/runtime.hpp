@@ -29,7 +29,7 @@ enum When { W_ALL, W_ALPHA, W_ALPHA_ITER, W_POWER };
 struct Stage { int kind, arg, when, iter; };
 
 struct LaunchRec {
-  int kind, arg, first, count, prec, ncb, toff;
+  int kind, arg, first, count, prec, ncb, toff, maxnb;
   unsigned grid;
 };
 
