@@ -19,10 +19,10 @@ enum Prec : int { F64 = 0, F32 = 1, B3 = 2 };
 // Tiling constants.  The pass kernels use 16x16 MFMA tiles; a wave owns RB row blocks of 16
 // rows and every column block of the panel.
 constexpr int WAVE = 64;
-constexpr int PASS_THREADS = 256;             // 4 waves
-constexpr int PASS_BM_F = 128;                // rows per tile, FP32 / BF16X3 (RB = 2)
-constexpr int PASS_BM_D = 64;                 // rows per tile, FP64 (RB = 1)
-constexpr int PASS_BK_F = 64;                 // K per LDS stage, FP32 / BF16X3
+constexpr int PASS_THREADS = 256;             // FP64 pass: 4 waves
+constexpr int PASS_BM_F = 256;                // rows per tile, FP32 / BF16X3 (8 waves)
+constexpr int PASS_BM_D = 64;                 // rows per tile, FP64 (16 per wave)
+constexpr int PASS_BK_F = 64;                 // K chunk granularity, FP32 / BF16X3
 constexpr int PASS_BK_D = 32;                 // K per LDS stage, FP64
 constexpr int PANEL_ALIGN = 64;               // panel leading dimension multiple
 constexpr int RPAD = 32;                      // panel column padding multiple

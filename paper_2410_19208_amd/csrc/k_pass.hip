@@ -2,46 +2,39 @@
 // scaled matrix B = (A + alpha I)/alpha applied without forming it).  Used for the sketch
 // (Z = Omega), the power iterations (Z = Q) and the compression pass (Z = Q).
 //
-// Design (gfx950): a workgroup of 4 waves owns BM rows of A and every column of the n x r
-// panel.  A streams from HBM straight into registers in MFMA operand order (each lane reads
-// KPL consecutive elements of one row); the BK x r slice of Z is staged through LDS and
-// shared by the 4 waves.  K is split into `split` chunks; with split = 8 the chunk index
-// equals the XCD of the workgroup (blocks are dealt round-robin to the 8 XCDs), so each
-// XCD's L2 holds only its own 1/8 of Z.  Partials are summed in a fixed order by
-// k_pass_reduce, so results do not depend on scheduling.
+// Every pass streams A once from HBM; the n x r panel Z is re-read from L2 by every row tile.
+// K is split into `split` chunks (at most 8); workgroups are dealt round-robin to the 8 XCDs
+// and the tile index is chunk-minor, so with split = 8 every workgroup of one XCD works on the
+// same K chunk and that XCD's L2 holds only its 1/8 of Z.  Partials are summed in a fixed
+// order by k_pass_reduce, so results do not depend on scheduling.
 //
-// Precisions: FP64 -> v_mfma_f64_16x16x4f64; FP32 -> v_mfma_f32_16x16x4f32; BF16X3 ->
-// v_mfma_f32_16x16x32_bf16 on the splits x = hi + lo (hi = bf16(x), lo = bf16(x - hi)),
-// accumulating hi*hi + hi*lo + lo*hi in FP32 (the lo*lo term, ~2^-16 relative, is dropped).
+// FP32 / BF16X3 (k_pass_lds): 8 waves own a 256-row tile and all r columns; each wave computes
+// a 64-row x r/2 block (4 x r/32 MFMA tiles), which balances the LDS bytes read per MFMA
+// between the A and Z operands.  Each K step of 32 moves the A slice (256 x 32 FP32) and the Z
+// slice (32 x r) from global memory straight into LDS (global_load_lds_dwordx4, no VGPR
+// round trip), double-buffered so the loads of step s+1 overlap the MFMAs of step s; one
+// barrier per step.  Slots inside each 1 KB block are XOR-swizzled so every 16-lane LDS read
+// of an MFMA operand touches 16 distinct 16-byte bank groups.
+//   FP32   -> v_mfma_f32_16x16x4f32;
+//   BF16X3 -> v_mfma_f32_16x16x32_bf16 on the splits x = hi + lo (hi = bf16(x),
+//             lo = bf16(x - hi)), accumulating hi*hi + hi*lo + lo*hi in FP32 (the lo*lo term,
+//             ~2^-16 relative, is dropped).  A is split in registers after the LDS read; Z is
+//             stored pre-split.
+// FP64 (k_pass): 4 waves own a 64-row tile; A goes to registers in MFMA operand order, the
+// Z slice through LDS; v_mfma_f64_16x16x4f64 (this path is MFMA bound).
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace psd {
 
-template <int PREC> struct PassCfg;
-template <> struct PassCfg<F64> {
-  typedef double TA; typedef f64x4 Acc;
-  static constexpr int RB = 1, BM = PASS_BM_D, BK = PASS_BK_D, ESZ = 8, NBUF = 1;
-};
-template <> struct PassCfg<F32> {
-  typedef float TA; typedef f32x4 Acc;
-  static constexpr int RB = 2, BM = PASS_BM_F, BK = PASS_BK_F, ESZ = 4, NBUF = 1;
-};
-template <> struct PassCfg<B3> {
-  typedef float TA; typedef f32x4 Acc;
-  static constexpr int RB = 2, BM = PASS_BM_F, BK = PASS_BK_F, ESZ = 2, NBUF = 2;
-};
-
-template <int PREC, int NCB>
+// ---------------------------------------------------------------- FP64: register A, LDS Z
+template <int NCB>
 __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict__ probs,
                                                          const int* __restrict__ tstart, int nprob) {
-  typedef PassCfg<PREC> C;
-  typedef typename C::TA TA;
-  typedef typename C::Acc Acc;
-  constexpr int RB = C::RB, BM = C::BM, BK = C::BK, KPL = BK / 4, NC = NCB * 16;
-  constexpr int CSTRIDE = BK * C::ESZ + 16;   // bytes per LDS column (padded against bank conflicts)
-  constexpr int CH = BK * C::ESZ / 16;         // 16-byte chunks per column
-  __shared__ __attribute__((aligned(16))) unsigned char lds[C::NBUF * NC * CSTRIDE];
+  constexpr int BM = PASS_BM_D, BK = PASS_BK_D, KPL = BK / 4, NC = NCB * 16;
+  constexpr int CSTRIDE = BK * 8 + 16;   // bytes per LDS column (padded against bank conflicts)
+  constexpr int CH = BK * 8 / 16;        // 16-byte chunks per column
+  __shared__ __attribute__((aligned(16))) unsigned char lds[NC * CSTRIDE];
 
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
@@ -54,144 +47,278 @@ __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict
   const int kend = min(n, kbeg + p.kchunk);
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int lrow = lane & 15, kg = lane >> 4;
-  const TA* __restrict__ A = (const TA*)p.A;
+  const double* __restrict__ A = (const double*)p.A;
   const int64_t lda = p.lda;
 
-  Acc acc[RB][NCB];
+  f64x4 acc[NCB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = Acc{0, 0, 0, 0};
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = f64x4{0, 0, 0, 0};
 
   const bool rows_full = (m0 + BM <= n) && p.avec;
-  int rowg[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) rowg[rb] = m0 + wave * 16 * RB + rb * 16 + lrow;
+  const int rowg = m0 + wave * 16 + lrow;
 
   for (int kk = kbeg; kk < kend; kk += BK) {
-    // ---- A fragments: lane (row, kg) holds A[row][kk + kg*KPL .. + KPL)
-    TA a[RB][KPL];
+    // ---- A fragment: lane (row, kg) holds A[row][kk + kg*KPL .. + KPL)
+    double a[KPL];
     const int c0 = kk + kg * KPL;
     if (rows_full && kk + BK <= n) {
+      const double* src = A + (int64_t)rowg * lda + c0;
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const TA* src = A + (int64_t)rowg[rb] * lda + c0;
-        if constexpr (PREC == F64) {
-#pragma unroll
-          for (int v = 0; v < KPL; v += 2) {
-            f64x2 x = __builtin_nontemporal_load((const f64x2*)(src + v));
-            a[rb][v] = x[0]; a[rb][v + 1] = x[1];
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < KPL; v += 4) {
-            f32x4 x = __builtin_nontemporal_load((const f32x4*)(src + v));
-            a[rb][v] = x[0]; a[rb][v + 1] = x[1]; a[rb][v + 2] = x[2]; a[rb][v + 3] = x[3];
-          }
-        }
+      for (int v = 0; v < KPL; v += 2) {
+        f64x2 x = __builtin_nontemporal_load((const f64x2*)(src + v));
+        a[v] = x[0]; a[v + 1] = x[1];
       }
     } else {
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int v = 0; v < KPL; ++v) {
-          const int col = c0 + v;
-          a[rb][v] = (rowg[rb] < n && col < n) ? A[(int64_t)rowg[rb] * lda + col] : (TA)0;
-        }
-    }
-
-    // ---- Z slice [kk, kk+BK) x [0, NC) into LDS (column-major, padded)
-    for (int c = threadIdx.x; c < C::NBUF * NC * CH; c += PASS_THREADS) {
-      const int buf = c / (NC * CH);
-      const int rem = c - buf * NC * CH;
-      const int col = rem / CH, ch = rem - col * CH;
-      const unsigned char* src;
-      if constexpr (PREC == B3) {
-        const bf16* z = buf ? p.zlo : p.zhi;
-        src = (const unsigned char*)(z + (int64_t)col * ld + kk) + ch * 16;
-      } else {
-        src = (const unsigned char*)((const TA*)p.zm + (int64_t)col * ld + kk) + ch * 16;
+      for (int v = 0; v < KPL; ++v) {
+        const int col = c0 + v;
+        a[v] = (rowg < n && col < n) ? A[(int64_t)rowg * lda + col] : 0.0;
       }
-      *(uint4*)(lds + (buf * NC + col) * CSTRIDE + ch * 16) = *(const uint4*)src;
+    }
+    // ---- Z slice [kk, kk+BK) x [0, NC) into LDS (column-major, padded)
+    for (int c = threadIdx.x; c < NC * CH; c += PASS_THREADS) {
+      const int col = c / CH, ch = c - col * CH;
+      const unsigned char* src = (const unsigned char*)((const double*)p.zm + (int64_t)col * ld + kk) + ch * 16;
+      *(uint4*)(lds + col * CSTRIDE + ch * 16) = *(const uint4*)src;
     }
     __syncthreads();
-
-    // ---- MFMA over the slice
-    if constexpr (PREC == B3) {
 #pragma unroll
-      for (int ks = 0; ks < BK / 32; ++ks) {
-        bf16x8 ahi[RB], alo[RB];
+    for (int t2 = 0; t2 < KPL; t2 += 2) {
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float x = a[rb][ks * 8 + e];
-            const bf16 h = (bf16)x;
-            ahi[rb][e] = h;
-            alo[rb][e] = (bf16)(x - (float)h);
-          }
-        const int koff = (kg * KPL + ks * 8) * 2;
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int col = cb * 16 + lrow;
-          const bf16x8 bhi = *(const bf16x8*)(lds + col * CSTRIDE + koff);
-          const bf16x8 blo = *(const bf16x8*)(lds + (NC + col) * CSTRIDE + koff);
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
-          }
-        }
-      }
-    } else if constexpr (PREC == F32) {
-#pragma unroll
-      for (int t4 = 0; t4 < KPL; t4 += 4) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int col = cb * 16 + lrow;
-          const float4 b = *(const float4*)(lds + col * CSTRIDE + (kg * KPL + t4) * 4);
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][t4 + 0], b.x, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][t4 + 1], b.y, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][t4 + 2], b.z, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][t4 + 3], b.w, acc[rb][cb], 0, 0, 0);
-          }
-        }
-      }
-    } else {
-#pragma unroll
-      for (int t2 = 0; t2 < KPL; t2 += 2) {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int col = cb * 16 + lrow;
-          const double2 b = *(const double2*)(lds + col * CSTRIDE + (kg * KPL + t2) * 8);
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][t2 + 0], b.x, acc[rb][cb], 0, 0, 0);
-            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][t2 + 1], b.y, acc[rb][cb], 0, 0, 0);
-          }
-        }
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int col = cb * 16 + lrow;
+        const double2 b = *(const double2*)(lds + col * CSTRIDE + (kg * KPL + t2) * 8);
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t2 + 0], b.x, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t2 + 1], b.y, acc[cb], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
   // ---- partial tile: lane holds rows acc_row(kg, v) of its 16-row block, column cb*16 + lrow
-  TA* __restrict__ out = (TA*)p.part + (int64_t)s * p.rpad * ld;
+  double* __restrict__ out = (double*)p.part + (int64_t)s * p.rpad * ld;
+  const int rbase = m0 + wave * 16;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    const int rbase = m0 + wave * 16 * RB + rb * 16;
+  for (int cb = 0; cb < NCB; ++cb) {
+    double* dst = out + (int64_t)(cb * 16 + lrow) * ld + rbase;
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      TA* dst = out + (int64_t)(cb * 16 + lrow) * ld + rbase;
-      if constexpr (PREC == F64) {
+    for (int v = 0; v < 4; ++v) dst[acc_row<true>(kg, v)] = acc[cb][v];
+  }
+}
+
+// ---------------------------------------------------------------- FP32 / BF16X3: LDS ring
+constexpr int PL_THREADS = 512;                  // 8 waves: 4 row groups x 2 column halves
+constexpr int PL_BM = PASS_BM_F;                 // 256 rows per tile (64 per row group)
+constexpr int PL_BK = 32;                        // K per step
+constexpr int PL_ABYTES = PL_BM * PL_BK * 4;     // A slice: 32 blocks of 1 KB (8 rows each)
+
+// LDS bytes of one step: A slice + Z slice (2 KB per 16 columns: hi and lo, or FP32).
+__host__ __device__ constexpr int pl_stage_bytes(int ncb) { return PL_ABYTES + ncb * 2048; }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// 16 bytes per lane from global memory into LDS at dst + 16 * lane (dst wave-uniform).
+__device__ __forceinline__ void dma16(const void* g, unsigned char* dst) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void*)dst, 16, 0, 0);
+}
+
+// Operand pointers and sizes of one pass, held in registers (the descriptor is read once).
+struct PlArgs {
+  const float* A; int64_t lda;
+  const void* z0; const void* z1;   // BF16X3: hi, lo; FP32: the panel (z1 unused)
+  int n, ld, avec;
+};
+
+// Issue the loads of step k0 into `stage`.
+//   A block b (rows 8b .. 8b+7 of the tile): row i at byte (i % 8) * 128, 16-byte slot s
+//     holds the 4 floats of chunk s ^ ((i % 16) / 2), i.e. columns k0 + 4c .. +3.
+//   Z, BF16X3: blocks 0..NCB-1 hold hi, NCB..2NCB-1 lo; block cb holds columns
+//     16cb .. 16cb+15 at 64 bytes each; slot s of column j holds chunk s ^ ((j % 16) / 4)
+//     (bf16 rows k0 + 8c .. +7).
+//   Z, FP32: block b holds columns 8b .. 8b+7 at 128 bytes each; slot s of column j holds
+//     chunk s ^ ((j % 16) / 2) (rows k0 + 4c .. +3).
+// A rows past n are clamped to n - 1 (their outputs are never stored); A chunks starting at or
+// past n read the row's first chunk instead and are zeroed after the LDS read.  Z rows in
+// [n, ld) are zero in every panel.
+template <int PREC, int NCB>
+__device__ __forceinline__ void pl_issue(const PlArgs& g, unsigned char* stage, int m0, int k0, int wave,
+                                         int lane) {
+  const int n = g.n;
+  if (g.avec) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[acc_row<true>(kg, v)] = acc[rb][cb][v];
-      } else {
-        *(float4*)(dst + 4 * kg) = float4{acc[rb][cb][0], acc[rb][cb][1], acc[rb][cb][2], acc[rb][cb][3]};
+    for (int u = 0; u < 4; ++u) {
+      const int blk = wave * 4 + u;
+      const int i = blk * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ ((i & 15) >> 1);
+      const int row = min(m0 + i, n - 1);
+      const int col = k0 + 4 * c;
+      dma16(g.A + (int64_t)row * g.lda + (col < n ? col : 0), stage + blk * 1024);
+    }
+  } else {
+    // rows not 16-byte aligned: element loads through VGPRs, same LDS layout
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int blk = wave * 4 + u;
+      const int i = blk * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ ((i & 15) >> 1);
+      const int row = min(m0 + i, n - 1);
+      const int col = k0 + 4 * c;
+      const float* src = g.A + (int64_t)row * g.lda;
+      f32x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (col + e < n) ? src[col + e] : 0.0f;
+      *(f32x4*)(stage + blk * 1024 + lane * 16) = v;
+    }
+  }
+  unsigned char* zs = stage + PL_ABYTES;
+#pragma unroll
+  for (int u = 0; u < (2 * NCB + 7) / 8; ++u) {
+    const int b = wave + 8 * u;
+    if (b >= 2 * NCB) break;
+    if constexpr (PREC == B3) {
+      const bf16* z = (const bf16*)((b < NCB) ? g.z0 : g.z1);
+      const int cb = (b < NCB) ? b : b - NCB;
+      const int j = lane >> 2;
+      const int c = (lane & 3) ^ (j >> 2);
+      dma16(z + (int64_t)(cb * 16 + j) * g.ld + k0 + 8 * c, zs + b * 1024);
+    } else {
+      const float* z = (const float*)g.z0;
+      const int col = b * 8 + (lane >> 3);
+      const int c = (lane & 7) ^ ((col & 15) >> 1);
+      dma16(z + (int64_t)col * g.ld + k0 + 4 * c, zs + b * 1024);
+    }
+  }
+}
+
+// MFMAs of one step.  Lane (li, kg) of an operand holds K indices 8kg .. 8kg+7 of the step.
+template <int PREC, int NCB>
+__device__ __forceinline__ void pl_compute(const unsigned char* stage, int wr, int wc, int lane, int kvalid,
+                                           f32x4 (&acc)[4][NCB / 2]) {
+  constexpr int NCH = NCB / 2;
+  const int li = lane & 15, kg = lane >> 4;
+  const unsigned char* zs = stage + PL_ABYTES;
+  // A fragments: rows wr*64 + rb*16 + li (so row % 16 == li)
+  f32x4 a0[4], a1[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int i = wr * 64 + rb * 16 + li;
+    const unsigned char* rowp = stage + (i >> 3) * 1024 + (i & 7) * 128;
+    a0[rb] = *(const f32x4*)(rowp + (((2 * kg) ^ (li >> 1)) << 4));
+    a1[rb] = *(const f32x4*)(rowp + (((2 * kg + 1) ^ (li >> 1)) << 4));
+  }
+  if (kvalid < PL_BK) {   // last step of a ragged K range: zero A past the end
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (8 * kg + e >= kvalid) a0[rb][e] = 0.0f;
+        if (8 * kg + 4 + e >= kvalid) a1[rb][e] = 0.0f;
       }
+  }
+  if constexpr (PREC == B3) {
+    bf16x8 ahi[4], alo[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = (e < 4) ? a0[rb][e] : a1[rb][e - 4];
+        const bf16 h = (bf16)x;
+        ahi[rb][e] = h;
+        alo[rb][e] = (bf16)(x - (float)h);
+      }
+    const int zoff = li * 64 + ((kg ^ (li >> 2)) << 4);
+#pragma unroll
+    for (int cb = 0; cb < NCH; ++cb) {
+      const int gcb = wc * NCH + cb;
+      const bf16x8 bhi = *(const bf16x8*)(zs + gcb * 1024 + zoff);
+      const bf16x8 blo = *(const bf16x8*)(zs + (NCB + gcb) * 1024 + zoff);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
+    }
+  } else {
+    const int zoff0 = (li & 7) * 128 + (((2 * kg) ^ (li >> 1)) << 4);
+    const int zoff1 = (li & 7) * 128 + (((2 * kg + 1) ^ (li >> 1)) << 4);
+#pragma unroll
+    for (int cb = 0; cb < NCH; ++cb) {
+      const int blk = 2 * (wc * NCH + cb) + (li >> 3);
+      const f32x4 b0 = *(const f32x4*)(zs + blk * 1024 + zoff0);
+      const f32x4 b1 = *(const f32x4*)(zs + blk * 1024 + zoff1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[rb][e], b0[e], acc[rb][cb], 0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[rb][e], b1[e], acc[rb][cb], 0, 0, 0);
+    }
+  }
+}
+
+template <int PREC, int NCB>
+__global__ __launch_bounds__(PL_THREADS, 1) void k_pass_lds(const Prob* __restrict__ probs,
+                                                           const int* __restrict__ tstart, int nprob) {
+  static_assert(NCB % 2 == 0, "panel widths are multiples of 32 columns");
+  constexpr int NCH = NCB / 2;
+  constexpr int SB = pl_stage_bytes(NCB);
+  extern __shared__ __attribute__((aligned(1024))) unsigned char smem[];
+
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int t = blockIdx.x - tstart[pi];
+  if (t >= p.npass_tiles) return;
+  const int s = t % p.split;
+  const int m0 = (t / p.split) * PL_BM;
+  const int n = p.n, ld = p.ld;
+  const int kbeg = s * p.kchunk;
+  const int kend = min(n, kbeg + p.kchunk);
+  const int nsteps = (kend - kbeg + PL_BK - 1) / PL_BK;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wr = wave & 3, wc = wave >> 2;
+
+  f32x4 acc[4][NCH];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NCH; ++cb) acc[rb][cb] = f32x4{0, 0, 0, 0};
+
+  PlArgs g;
+  g.A = (const float*)p.A; g.lda = p.lda;
+  g.z0 = (PREC == B3) ? (const void*)p.zhi : p.zm;
+  g.z1 = (PREC == B3) ? (const void*)p.zlo : p.zm;
+  g.n = n; g.ld = ld; g.avec = p.avec;
+  float* __restrict__ out = (float*)p.part + (int64_t)s * p.rpad * ld;
+
+  pl_issue<PREC, NCB>(g, smem, m0, kbeg, wave, lane);
+  for (int st = 0; st < nsteps; ++st) {
+    // this wave's loads of step st have landed; the barrier publishes everyone's, and also
+    // ends every wave's reads of the other buffer (step st - 1), which step st + 1 overwrites
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+    const int k0 = kbeg + st * PL_BK;
+    if (st + 1 < nsteps) pl_issue<PREC, NCB>(g, smem + ((st + 1) & 1) * SB, m0, k0 + PL_BK, wave, lane);
+    pl_compute<PREC, NCB>(smem + (st & 1) * SB, wr, wc, lane, kend - k0, acc);
+  }
+
+  // ---- partial tile: lane (li, kg) holds rows 4kg .. 4kg+3 of block (rb, cb), column li
+  const int li = lane & 15, kg = lane >> 4;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int rbase = m0 + wr * 64 + rb * 16;
+    if (rbase >= n) break;
+#pragma unroll
+    for (int cb = 0; cb < NCH; ++cb) {
+      float* dst = out + (int64_t)((wc * NCH + cb) * 16 + li) * ld + rbase + 4 * kg;
+      *(f32x4*)dst = acc[rb][cb];
     }
   }
 }
@@ -234,21 +361,43 @@ int tiles_pass(const Prob& p) {
 }
 int tiles_reduce(const Prob& p) { return (int)(((int64_t)p.rpad * p.ld + 1023) / 1024); }
 
-template <int PREC>
-static void launch_pass_prec(const Launch& L, int ncb) {
+#define PSD_NCB_EVEN(X) X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16)
+
+void launch_pass(const Launch& L, int prec, int ncb) {
+  if (prec == F64) {
+    switch (ncb) {
+#define PSD_CASE(N) case N: hipLaunchKernelGGL((k_pass<N>), dim3(L.grid), dim3(PASS_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob); break;
+      PSD_NCB_EVEN(PSD_CASE)
+#undef PSD_CASE
+      default: break;
+    }
+    return;
+  }
   switch (ncb) {
-#define PSD_CASE(N) case N: hipLaunchKernelGGL((k_pass<PREC, N>), dim3(L.grid), dim3(PASS_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob); break;
-    PSD_CASE(1) PSD_CASE(2) PSD_CASE(3) PSD_CASE(4) PSD_CASE(5) PSD_CASE(6) PSD_CASE(7) PSD_CASE(8)
-    PSD_CASE(9) PSD_CASE(10) PSD_CASE(11) PSD_CASE(12) PSD_CASE(13) PSD_CASE(14) PSD_CASE(15) PSD_CASE(16)
+#define PSD_CASE(N)                                                                                              \
+  case N:                                                                                                        \
+    if (prec == F32)                                                                                             \
+      hipLaunchKernelGGL((k_pass_lds<F32, N>), dim3(L.grid), dim3(PL_THREADS), 2 * pl_stage_bytes(N), L.stream, \
+                         L.probs, L.tstart, L.nprob);                                                            \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_pass_lds<B3, N>), dim3(L.grid), dim3(PL_THREADS), 2 * pl_stage_bytes(N), L.stream,  \
+                         L.probs, L.tstart, L.nprob);                                                            \
+    break;
+    PSD_NCB_EVEN(PSD_CASE)
 #undef PSD_CASE
     default: break;
   }
 }
 
-void launch_pass(const Launch& L, int prec, int ncb) {
-  if (prec == F64) launch_pass_prec<F64>(L, ncb);
-  else if (prec == F32) launch_pass_prec<F32>(L, ncb);
-  else launch_pass_prec<B3>(L, ncb);
+// Opt the LDS-ring pass kernels into more than 64 KB of dynamic LDS.
+void pass_init() {
+#define PSD_ATTR(N)                                                                                    \
+  hipFuncSetAttribute((const void*)k_pass_lds<F32, N>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                      2 * pl_stage_bytes(N));                                                          \
+  hipFuncSetAttribute((const void*)k_pass_lds<B3, N>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
+                      2 * pl_stage_bytes(N));
+  PSD_NCB_EVEN(PSD_ATTR)
+#undef PSD_ATTR
 }
 
 void launch_pass_reduce(const Launch& L) {

@@ -36,6 +36,7 @@ void launch_gauss(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t cou
 // (+ scaled epilogue (Y + alpha Z)/alpha).
 void launch_pass(const Launch& L, int prec, int ncb);
 void launch_pass_reduce(const Launch& L);
+void pass_init();                     // dynamic-LDS attributes of the pass kernels
 
 // Gram X^T Y (mode 0: Y^T Y of the pass output, upper tiles; 1: Q1^T Q1; 2: Q^T Y full,
 // symmetrised) and its deterministic reduction.

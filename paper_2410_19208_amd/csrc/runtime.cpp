@@ -45,11 +45,14 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.es = (pl.prec == F64) ? 8 : 4;
   pl.ncb = pl.rpad / 16;
   pl.alpha_mode = alpha_mode;
-  // split-K: enough workgroups to fill 256 CUs twice, at most 8 (one K chunk per XCD)
+  // split-K, at most 8 (one K chunk per XCD).  FP64: enough workgroups to fill 256 CUs twice.
+  // FP32 / BF16X3 (one 8-wave workgroup per CU): 8 chunks of at least 64 columns, so each
+  // XCD's L2 holds one chunk of the panel.
   const int bm = (pl.prec == F64) ? PASS_BM_D : PASS_BM_F;
   const int bk = (pl.prec == F64) ? PASS_BK_D : PASS_BK_F;
   const int mt = (n + bm - 1) / bm;
-  int split = std::min(8, std::max(1, (512 + mt - 1) / mt));
+  int split = (pl.prec == F64) ? std::min(8, std::max(1, (512 + mt - 1) / mt))
+                               : std::min(8, std::max(1, (n + 63) / 64));
   int kchunk = rup((n + split - 1) / split, bk);
   split = (n + kchunk - 1) / kchunk;
   pl.split = split;
@@ -312,7 +315,7 @@ static void kernel_init_once() {
   hipGetDevice(&dev);
   std::lock_guard<std::mutex> g(mu);
   if ((int)done.size() <= dev) done.resize(dev + 1, false);
-  if (!done[dev]) { rebuild_init(); apply_init(); done[dev] = true; }
+  if (!done[dev]) { rebuild_init(); apply_init(); pass_init(); done[dev] = true; }
 }
 
 // ------------------------------------------------------------------------------ kernel timing

@@ -71,6 +71,30 @@ def test_parity_ragged(prec, variant, alpha, q):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("variant,alpha", [("plain", 0.0), ("scaled", 0.0)])
+@pytest.mark.parametrize("lda", [780, 800])
+def test_parity_ragged_padded_rows(prec, variant, alpha, lda):
+    """n = 777 stored in a wider buffer (row stride lda, 16-byte aligned rows) whose padding
+    columns hold NaN: the ragged last tile and K step must never let them into the result."""
+    import torch
+    from paper_2410_19208_amd.torch_api import Projector
+    dev = _gpu.device()
+    n, k, p, q = 777, 40, 12, 1
+    A, lam, U = matrix("medium", n, 5, n_pos=60)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    buf = torch.full((n, lda), float("nan"), dtype=dt, device=dev)
+    buf[:, :n] = _gpu.to_dev(A.astype(_gpu.storage(prec)), dev)
+    proj = Projector(n, k, p, q, variant, prec, seed=3, alpha=alpha, device=dev)
+    P = proj(buf[:, :n]).cpu().numpy()
+    res = proj.result()
+    ref = run_oracle(A, k, p, q, variant, prec, seed=3, alpha=alpha)
+    assert res.status == 0
+    err = parity(P, ref, A)
+    print(f"padded lda={lda} {prec} {variant}: parity {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_exact_recovery(prec):
     """rank(A) <= k+p: the projection is A_+ (closed form) to working precision."""
     n = 300
