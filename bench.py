@@ -152,8 +152,8 @@ def main() -> int:
     d = kern[dom]
     bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
     if dom == "k_gemv":
-        alg = nn * es + 2 * n * 8.0
-        note = "A read once per product plus two FP64 vectors"
+        alg = n * (n + 1) / 2 * es + 2 * n * 8.0
+        note = "upper triangle of the symmetric A read once per product plus two FP64 vectors"
     elif dom == "k_pass":
         alg = nn * es  # A streamed once per pass (the Z panel is L2/MALL resident)
         note = "A read once per pass"

@@ -30,7 +30,7 @@ constexpr int GRAM_TILE = 32;                 // Gram output tile
 constexpr int GRAM_CHUNK = 1024;              // rows per Gram partial
 constexpr int RB_TILE = 128;                  // rebuild output tile (P)
 constexpr int APPLY_ROWS = 64;                // rows per apply/formw tile
-constexpr int GEMV_ROWS = 32;                 // rows per GEMV workgroup (8 per wave)
+constexpr int GEMV_TILE = 256;                // GEMV tile edge (upper-triangle tiles of A)
 constexpr int NSCAL = 16;
 constexpr int NISCAL = 16;
 
@@ -62,7 +62,8 @@ struct Prob {
   double* G; double* F; double* C; double* H; double* V;  // rpad x rpad, column-major
   double* evals; double* tau; double* td; double* te; double* wts; double* xt;  // eig scratch
   double* vec;                     // power vectors: 2 x ld
-  double* vpart;                   // GEMV block partial sums
+  double* vpart;                   // GEMV: sum of squares per block row
+  double* gvp;                     // GEMV tile partials: nb x nb x GEMV_TILE
   double* scal;                    // NSCAL doubles
   int32_t* iscal;                  // NISCAL ints
   int32_t* drop;                   // rpad flags

@@ -2,85 +2,100 @@
 //
 // One launch of k_gemv computes y = X v - shift v with v = y_prev * inv_prev (the previous
 // product scaled to unit norm; the first product uses the raw Gaussian start vector) and the
-// norm ||y||.  The shift of Alg. 5 line 2 is applied to the vector, so X - sigma_1 I is never
-// formed.  Vectors and accumulation are FP64 for every storage precision of A.
-// The norm is reduced deterministically: each block writes its partial sum of squares, and
-// the last block to finish (integer ticket counter) adds the partials in block order.
+// norm ||y||.  The shift of Alg. 5 is applied to the vector, so X - sigma_1 I is never formed.
+// Vectors and accumulation are FP64 for every storage precision of A.
+//
+// X is symmetric, so only its upper triangle is read: k_gemv gives one workgroup per 256 x 256
+// tile X_IJ (I <= J) and, from one read of it, forms both X_IJ v_J (row sums, contribution to
+// block row I) and X_IJ^T v_I (column sums, contribution to block row J; skipped on the
+// diagonal tile).  That halves the HBM bytes of a product.  Each block row gets exactly nb
+// contributions, stored in a partial array; k_gemv_finish (one workgroup per block row) adds
+// them in a fixed order, applies the shift and stores the row's sum of squares, and the last
+// block row to finish (integer ticket) adds those in block order and forms the norm.  No
+// result depends on scheduling.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace psd {
 
-constexpr int GEMV_THREADS = 256;
-constexpr int ROWS_PER_WAVE = GEMV_ROWS / 4;   // 8
+constexpr int GEMV_THREADS = 256;   // 4 waves x 64 rows of a tile
 
-template <typename T>
-__device__ void gemv_block(const Prob& p, int t, int last) {
+// Tile t -> (I, J), I <= J: t enumerates the lower-triangle pairs (a, b), b <= a, row by row,
+// and (I, J) = (b, a).
+__device__ __forceinline__ void gemv_tile_ij(int t, int& I, int& J) {
+  int a = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= t) ++a;
+  while (a * (a + 1) / 2 > t) --a;
+  J = a;
+  I = t - a * (a + 1) / 2;
+}
+
+// One halving stage: lanes with bit D set keep the upper M/2 rows, the others the lower M/2,
+// and each adds its partner's (lane ^ D) copy of the rows it keeps.
+template <int M, int D, int RB>
+__device__ __forceinline__ void halve(double (&x)[RB], int lane) {
+  const bool up = (lane & D) != 0;
+#pragma unroll
+  for (int k = 0; k < M / 2; ++k) {
+    const double lo = x[k], hi = x[k + M / 2];
+    const double keep = up ? hi : lo;
+    const double send = up ? lo : hi;
+    x[k] = keep + __shfl_xor(send, D, 64);
+  }
+  if constexpr (M > 2) halve<M / 2, D / 2, RB>(x, lane);
+}
+
+// Sum of x over the 64 lanes of a wave for RB rows at once: after the call, x[0] of lane l
+// holds the full sum of row l >> (6 - log2 RB).  Recursive halving over lane bits 5, 4, ...
+// then a butterfly over the remaining low bits; the addition order is fixed.
+template <int RB>
+__device__ __forceinline__ void reduce_scatter(double (&x)[RB], int lane) {
+  halve<RB, 32, RB>(x, lane);
+#pragma unroll
+  for (int d = 32 / RB; d > 0; d >>= 1) x[0] += __shfl_xor(x[0], d, 64);
+}
+
+// Fixed-order sum of the nb contributions of block row b, shift, store, sum of squares; the
+// last block row also forms the norm.
+__global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __restrict__ probs,
+                                                              const int* __restrict__ tstart, int nprob, int last) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int b = blockIdx.x - tstart[pi];
+  __shared__ double red[GEMV_THREADS / WAVE];
   const int n = p.n, ld = p.ld;
-  const int pp = p.iscal[I_PP] & 1;                 // ping-pong: read vec[pp], write vec[1-pp]
+  const int nb = (n + GEMV_TILE - 1) / GEMV_TILE;
+  const int pp = p.iscal[I_PP] & 1;
   const double* __restrict__ vin = p.vec + (int64_t)pp * ld;
   double* __restrict__ vout = p.vec + (int64_t)(1 - pp) * ld;
   const double inv = p.scal[S_INV];
   const double shift = p.scal[S_SHIFT];
-  const T* __restrict__ A = (const T*)p.A;
-  const int64_t lda = p.lda;
-  const int wave = wave_id(), lane = threadIdx.x & 63;
-  const int row0 = t * GEMV_ROWS + wave * ROWS_PER_WAVE;
-  __shared__ double red[4];
-
-  double acc[ROWS_PER_WAVE];
-#pragma unroll
-  for (int q = 0; q < ROWS_PER_WAVE; ++q) acc[q] = 0.0;
-  int rows[ROWS_PER_WAVE];
-#pragma unroll
-  for (int q = 0; q < ROWS_PER_WAVE; ++q) rows[q] = min(row0 + q, n - 1);   // clamp; masked below
-  // Rows that do not start 16-byte aligned are read with scalar loads (n4 = 0); otherwise
-  // 4-wide vector loads cover [0, n4) and scalar loads the tail [n4, n).
-  const int n4 = p.avec ? (n & ~3) : 0;
-  for (int j = lane * 4; j < n4; j += WAVE * 4) {
-    const double v0 = vin[j] * inv, v1 = vin[j + 1] * inv, v2 = vin[j + 2] * inv, v3 = vin[j + 3] * inv;
-#pragma unroll
-    for (int q = 0; q < ROWS_PER_WAVE; ++q) {
-      const T* src = A + (int64_t)rows[q] * lda + j;
-      if constexpr (sizeof(T) == 4) {
-        const f32x4 a = __builtin_nontemporal_load((const f32x4*)src);
-        acc[q] += (double)a[0] * v0 + (double)a[1] * v1 + (double)a[2] * v2 + (double)a[3] * v3;
-      } else {
-        const f64x2 a = __builtin_nontemporal_load((const f64x2*)src);
-        const f64x2 b = __builtin_nontemporal_load((const f64x2*)(src + 2));
-        acc[q] += a[0] * v0 + a[1] * v1 + b[0] * v2 + b[1] * v3;
-      }
-    }
+  const int x = threadIdx.x;
+  const int row = b * GEMV_TILE + x;
+  const double* __restrict__ part = p.gvp + (int64_t)b * nb * GEMV_TILE;
+  double y = 0.0;
+  if (row < n) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < nb; ++c) s += part[(int64_t)c * GEMV_TILE + x];
+    y = s - shift * (vin[row] * inv);
+    vout[row] = y;
   }
-  for (int j = n4 + lane; j < n; j += WAVE) {
-    const double vj = vin[j] * inv;
-#pragma unroll
-    for (int q = 0; q < ROWS_PER_WAVE; ++q) acc[q] += (double)A[(int64_t)rows[q] * lda + j] * vj;
-  }
-  double ss = 0.0;
-#pragma unroll
-  for (int q = 0; q < ROWS_PER_WAVE; ++q) {
-    const double s = wave_sum(acc[q]);
-    const int row = row0 + q;
-    if (row < n) {
-      const double y = s - shift * (vin[row] * inv);
-      if (lane == 0) vout[row] = y;
-      ss += y * y;
-    }
-  }
-  if (lane == 0) red[wave] = ss;
+  const double ss = wave_sum(y * y);
+  if ((x & 63) == 0) red[x >> 6] = ss;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nblk = (n + GEMV_ROWS - 1) / GEMV_ROWS;
-    p.vpart[t] = red[0] + red[1] + red[2] + red[3];
-    __threadfence();
+  if (x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < GEMV_THREADS / WAVE; ++w) tot += red[w];
+    p.vpart[b] = tot;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const int ticket = atomicAdd(&p.iscal[I_COUNTER], 1);
-    if (ticket == nblk - 1) {
-      __threadfence();
-      const volatile double* vp = p.vpart;
-      double tot = 0.0;
-      for (int b = 0; b < nblk; ++b) tot += vp[b];
-      const double nrm = sqrt(tot);
+    if (ticket == nb - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const double* vp = p.vpart;
+      double t2 = 0.0;
+      for (int r = 0; r < nb; ++r) t2 += vp[r];
+      const double nrm = sqrt(t2);
       p.scal[S_NRM] = nrm;
       p.scal[S_INV] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
       if (last == 1) p.scal[S_SIGMA1] = nrm;
@@ -91,13 +106,109 @@ __device__ void gemv_block(const Prob& p, int t, int last) {
   }
 }
 
+// RB rows per load batch: 16 for FP32 storage, 8 for FP64 (64 VGPRs of A in flight per lane).
+template <typename T, int RB>
+__device__ void gemv_tile(const Prob& p, int t) {
+  constexpr int LOGRB = (RB == 16) ? 4 : 3;
+  const int n = p.n, ld = p.ld;
+  const int nb = (n + GEMV_TILE - 1) / GEMV_TILE;
+  int I, J;
+  gemv_tile_ij(t, I, J);
+  const bool diag = (I == J);
+  const int pp = p.iscal[I_PP] & 1;                 // ping-pong: read vec[pp], write vec[1-pp]
+  const double* __restrict__ vin = p.vec + (int64_t)pp * ld;
+  const double inv = p.scal[S_INV];
+  const T* __restrict__ A = (const T*)p.A;
+  const int64_t lda = p.lda;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  __shared__ double cred[GEMV_THREADS / WAVE][GEMV_TILE];
+
+  // lane owns columns c0 .. c0+3 of the tile, the wave rows I*256 + wave*64 + [0, 64)
+  const int c0 = J * GEMV_TILE + 4 * lane;
+  double vj[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) vj[e] = (c0 + e < n) ? vin[c0 + e] * inv : 0.0;
+  // full tile columns and 16-byte aligned rows: vector loads; otherwise masked element loads
+  const bool vec = p.avec && (J * GEMV_TILE + GEMV_TILE <= n);
+  double yc[4] = {0.0, 0.0, 0.0, 0.0};
+  double* __restrict__ gvp = p.gvp;
+
+  // batch loads: rows r0 .. r0+RB-1 (clamped to n-1; rows past n are zeroed when used)
+  auto load = [&](T (&a)[RB][4], int r0) {
+    if (vec) {
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const T* src = A + (int64_t)min(r0 + q, n - 1) * lda + c0;
+        if constexpr (sizeof(T) == 4) {
+          const f32x4 x = __builtin_nontemporal_load((const f32x4*)src);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[q][e] = x[e];
+        } else {
+          const f64x2 x0 = __builtin_nontemporal_load((const f64x2*)src);
+          const f64x2 x1 = __builtin_nontemporal_load((const f64x2*)(src + 2));
+          a[q][0] = x0[0]; a[q][1] = x0[1]; a[q][2] = x1[0]; a[q][3] = x1[1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          a[q][e] = (r0 + q < n && c0 + e < n) ? A[(int64_t)(r0 + q) * lda + c0 + e] : (T)0;
+    }
+  };
+  const int rw = I * GEMV_TILE + wave * 64;   // first row of this wave (wave-uniform)
+  T a[RB][4], an[RB][4];
+  if (rw < n) load(a, rw);
+#pragma unroll 1
+  for (int bt = 0; bt < 64 / RB; ++bt) {
+    const int r0 = rw + bt * RB;
+    if (r0 >= n) break;
+    if (bt + 1 < 64 / RB && r0 + RB < n) load(an, r0 + RB);
+    double rs[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      // rows past n (clamped loads) contribute nothing
+      const bool ok = (r0 + q < n);
+      double x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = ok ? (double)a[q][e] : 0.0;
+      rs[q] = x[0] * vj[0] + x[1] * vj[1] + x[2] * vj[2] + x[3] * vj[3];
+      if (!diag) {
+        const double vi = ok ? vin[r0 + q] * inv : 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) yc[e] += x[e] * vi;
+      }
+    }
+    reduce_scatter<RB>(rs, lane);
+    if ((lane & ((64 / RB) - 1)) == 0) {
+      const int rl = wave * 64 + bt * RB + (lane >> (6 - LOGRB));
+      gvp[((int64_t)I * nb + J) * GEMV_TILE + rl] = rs[0];
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[q][e] = an[q][e];
+  }
+  // column sums: this wave's rows -> LDS, then the 4 waves in order
+  if (!diag) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cred[wave][4 * lane + e] = yc[e];
+  }
+  __syncthreads();
+  if (!diag) {
+    const int c = threadIdx.x;
+    gvp[((int64_t)J * nb + I) * GEMV_TILE + c] = cred[0][c] + cred[1][c] + cred[2][c] + cred[3][c];
+  }
+}
+
 __global__ __launch_bounds__(GEMV_THREADS) void k_gemv(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                       int nprob, int last) {
+                                                       int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int t = blockIdx.x - tstart[pi];
-  if (p.prec == F64) gemv_block<double>(p, t, last);
-  else gemv_block<float>(p, t, last);
+  if (p.prec == F64) gemv_tile<double, 8>(p, t);
+  else gemv_tile<float, 16>(p, t);
 }
 
 // alpha = |sigma1 - sigma2| (Alg. 5 line 4); E_ALPHA unless positive and finite.
@@ -133,12 +244,20 @@ __global__ void k_finalize(const Prob* __restrict__ probs, const int* __restrict
   *p.res = out;
 }
 
-int tiles_gemv(const Prob& p) { return (p.n + GEMV_ROWS - 1) / GEMV_ROWS; }
+int tiles_gemv(const Prob& p) {
+  const int nb = (p.n + GEMV_TILE - 1) / GEMV_TILE;
+  return nb * (nb + 1) / 2;
+}
+int tiles_gemv_rows(const Prob& p) { return (p.n + GEMV_TILE - 1) / GEMV_TILE; }
 int tiles_vec(const Prob& p) { return (p.ld + 1023) / 1024; }
 int tiles_omega(const Prob& p) { return (int)(((int64_t)p.rpad * p.ld + 1023) / 1024); }
 
 void launch_gemv(const Launch& L, int last) {
-  hipLaunchKernelGGL(k_gemv, dim3(L.grid), dim3(GEMV_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, last);
+  (void)last;
+  hipLaunchKernelGGL(k_gemv, dim3(L.grid), dim3(GEMV_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+}
+void launch_gemv_finish(const Launch& L, int last) {
+  hipLaunchKernelGGL(k_gemv_finish, dim3(L.grid), dim3(GEMV_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, last);
 }
 void launch_alpha(const Launch& L) {
   hipLaunchKernelGGL(k_alpha, dim3(L.grid), dim3(64), 0, L.stream, L.probs, L.tstart, L.nprob);

@@ -23,6 +23,7 @@ int tiles_gram(const Prob& p, bool full);
 int tiles_small(const Prob& p);       // one block per problem
 int tiles_apply(const Prob& p);
 int tiles_gemv(const Prob& p);
+int tiles_gemv_rows(const Prob& p);  // one block per 256-row block row
 int tiles_bisect(const Prob& p);
 int tiles_invit(const Prob& p);
 int tiles_rebuild(const Prob& p);
@@ -60,6 +61,7 @@ void launch_finalize(const Launch& L);
 
 // Alg. 4/5 matrix-vector products.
 void launch_gemv(const Launch& L, int last);
+void launch_gemv_finish(const Launch& L, int last);
 void launch_alpha(const Launch& L);
 
 }  // namespace psd

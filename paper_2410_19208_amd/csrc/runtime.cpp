@@ -87,7 +87,9 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.o_te = take(PSDPROJ_MAX_RANK * 8);
   pl.o_wts = take(PSDPROJ_MAX_RANK * 8);
   pl.o_vec = take((size_t)2 * pl.ld * 8);
-  pl.o_vpart = take((size_t)(pl.ld / GEMV_ROWS + 1) * 8);
+  const size_t gnb = (size_t)(n + GEMV_TILE - 1) / GEMV_TILE;
+  pl.o_vpart = take(gnb * 8);
+  pl.o_gvp = take(gnb * gnb * GEMV_TILE * 8);
   pl.o_scal = take(NSCAL * 8);
   pl.o_iscal = take(NISCAL * 4);
   pl.o_drop = take(PSDPROJ_MAX_RANK * 4);
@@ -126,6 +128,7 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   p.evals = (double*)at(pl.o_evals); p.tau = (double*)at(pl.o_tau);
   p.td = (double*)at(pl.o_td); p.te = (double*)at(pl.o_te); p.wts = (double*)at(pl.o_wts);
   p.vec = (double*)at(pl.o_vec); p.vpart = (double*)at(pl.o_vpart);
+  p.gvp = (double*)at(pl.o_gvp);
   p.scal = (double*)at(pl.o_scal); p.iscal = (int32_t*)at(pl.o_iscal); p.drop = (int32_t*)at(pl.o_drop);
   p.res = res;
   p.npass_tiles = tiles_pass(p);
@@ -152,6 +155,7 @@ static int stage_tiles(const Prob& p, int kind) {
     case K_OMEGA: return tiles_omega(p);
     case K_PINIT: return tiles_vec(p);
     case K_GEMV: return tiles_gemv(p);
+    case K_GEMV_FIN: return tiles_gemv_rows(p);
     case K_PASS: return rup(tiles_pass(p), 8);
     case K_PRED: return tiles_reduce(p);
     case K_GRAM_SYM: return tiles_gram(p, false);
@@ -172,8 +176,12 @@ static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
   if (max_iters > 0) {
     for (int run = 0; run < 2; ++run) {
       add(K_PINIT, run, W_ALPHA, 0);
-      for (int it = 0; it < max_iters; ++it) add(K_GEMV, 0, W_ALPHA_ITER, it);
+      for (int it = 0; it < max_iters; ++it) {
+        add(K_GEMV, 0, W_ALPHA_ITER, it);
+        add(K_GEMV_FIN, 0, W_ALPHA_ITER, it);
+      }
       add(K_GEMV, run + 1, W_ALPHA, 0);
+      add(K_GEMV_FIN, run + 1, W_ALPHA, 0);
     }
     add(K_ALPHA, 0, W_ALPHA, 0);
   }
@@ -377,6 +385,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
       case K_OMEGA: launch_omega(L); break;
       case K_PINIT: launch_power_init(L, R.arg); break;
       case K_GEMV: launch_gemv(L, R.arg); break;
+      case K_GEMV_FIN: launch_gemv_finish(L, R.arg); break;
       case K_ALPHA: launch_alpha(L); break;
       case K_PASS: launch_pass(L, R.prec, R.ncb); break;
       case K_PRED: launch_pass_reduce(L); break;
@@ -404,7 +413,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
 static const char* const KIND_NAMES[K_NKINDS] = {
     "k_setup", "k_omega", "k_power_init", "k_gemv", "k_alpha", "k_pass", "k_pass_reduce", "k_gram",
     "k_gram_full", "k_gram_reduce", "k_chol", "k_apply", "k_tridiag", "k_bisect", "k_invit", "k_rebuild",
-    "k_finalize"};
+    "k_finalize", "k_gemv_finish"};
 
 psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp) {
   const int64_t n = pl.d.n;

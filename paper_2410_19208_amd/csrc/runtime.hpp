@@ -17,12 +17,12 @@ struct Plan {
   size_t header_single;   // header bytes of a single run
   size_t o_zm, o_zhi, o_zlo, o_y, o_part, o_q1, o_wf, o_whi, o_wlo, o_gpart;
   size_t o_G, o_F, o_C, o_H, o_V, o_xt, o_evals, o_tau, o_td, o_te, o_wts;
-  size_t o_vec, o_vpart, o_scal, o_iscal, o_drop;
+  size_t o_vec, o_vpart, o_gvp, o_scal, o_iscal, o_drop;
 };
 
 enum Kind {
   K_SETUP, K_OMEGA, K_PINIT, K_GEMV, K_ALPHA, K_PASS, K_PRED, K_GRAM_SYM, K_GRAM_FULL, K_GRED,
-  K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_NKINDS
+  K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_GEMV_FIN, K_NKINDS
 };
 enum When { W_ALL, W_ALPHA, W_ALPHA_ITER, W_POWER };
 
