@@ -108,13 +108,6 @@ __device__ __forceinline__ void upper_tile(int t, int nb, int& I, int& J) {
   J = i + rem;
 }
 
-// Register-resident symmetric r_pad x r_pad FP64 matrices (one workgroup of SYM_WAVES waves):
-// the upper-triangle 16x16 tiles are dealt round-robin to the waves (tile t -> wave t % SYM_WAVES,
-// slot t / SYM_WAVES); lane l of the owner holds row l%16, columns 4*(l/16) .. +3 of the tile.
-constexpr int SYM_WAVES = 8;
-constexpr int SYM_THREADS = SYM_WAVES * 64;
-constexpr int SYM_SLOTS = (PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2 / SYM_WAVES + 1;  // 9
-
 // Number of eigenvalues of T below x (Sturm sequence).
 __device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int r, double x,
                                            double pivmin) {

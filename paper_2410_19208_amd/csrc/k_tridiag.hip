@@ -1,14 +1,18 @@
 // Householder tridiagonalisation C = Q_H T Q_H^T of the compressed matrix (first half of the
 // symmetric eigensolve of Alg. 2 line 2 / Alg. 3 line 3), FP64, one workgroup per problem.
 //
-// The symmetric matrix lives in registers as upper-triangle 16x16 tiles (see SYM_* in
-// common.hpp).  Step j (j = 0 .. r-3):
+// The upper-triangle 16x16 tiles of the symmetric r_pad x r_pad matrix live in registers.  A
+// wave owns whole column blocks, paired as J and nb-1-J so every wave holds nb+1 tiles; lane l
+// of a tile holds row l%16, columns 4*(l/16) .. +3.  Step j (j = 0 .. r-3):
 //   1. the owners of row j publish it through LDS (double-buffered);
 //   2. every wave forms the reflector H_j = I - tau v v^T that maps C[j+1:, j] to beta e_1
 //      (redundantly, identical arithmetic in every wave, so no extra barrier);
-//   3. p = tau C2 v (C2 = trailing block) as per-tile partial row and column sums written to
-//      LDS and summed in a fixed order, K = tau/2 p^T v, w = p - K v;
+//   3. p = tau C2 v (C2 = trailing block): per tile, the row sums C_IJ v_J (a 4-lane reduction)
+//      go to LDS; the column sums C_IJ^T v_I accumulate in registers over a column block and
+//      are reduced once per block (16-lane reduce-scatter); p_i adds the nb row-block terms and
+//      the column-block term in a fixed order; K = tau/2 p^T v, w = p - K v;
 //   4. C2 -= v w^T + w v^T on the registers.
+// Tiles left of or above the trailing block are skipped (wave-uniform tests).
 // Outputs: diagonal d and off-diagonal e of T, tau_j, the reflector vectors v (entries j+2..r-1)
 // in column j of H, the Gershgorin interval, and the Sturm count nu of eigenvalues below the
 // clamp threshold (0 for Alg. 2, 1 for Alg. 3): only the r - nu eigenpairs above it are kept.
@@ -17,42 +21,78 @@
 
 namespace psd {
 
-template <int NS>   // register slots per wave (14: r_pad <= 224, 17: r_pad = 256)
-__global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                         int nprob) {
+constexpr int TD_WAVES = 8;
+constexpr int TD_THREADS = TD_WAVES * WAVE;
+constexpr int TD_NB = PSDPROJ_MAX_RANK / 16;   // 16 column blocks at most
+
+// Sum over the 16 lanes of a row group (lane bits 0..3) of c[0..3]: afterwards lane l holds the
+// full sum of c[(l >> 2) & 3] in c[0].  Halving over bits 3 and 2, then a butterfly over bits 1
+// and 0; fixed order.
+__device__ __forceinline__ void colsum16(double (&c)[4], int lane) {
+  {
+    const bool up = (lane & 8) != 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double lo = c[k], hi = c[k + 2];
+      const double keep = up ? hi : lo, send = up ? lo : hi;
+      c[k] = keep + __shfl_xor(send, 8, 64);
+    }
+  }
+  {
+    const bool up = (lane & 4) != 0;
+    const double keep = up ? c[1] : c[0], send = up ? c[0] : c[1];
+    c[0] = keep + __shfl_xor(send, 4, 64);
+  }
+  c[0] += __shfl_xor(c[0], 2, 64);
+  c[0] += __shfl_xor(c[0], 1, 64);
+}
+
+template <int NS>   // register slots per wave: nb + 1 (15: r_pad <= 224, 17: r_pad = 256)
+__global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__ probs, const int* __restrict__ tstart,
+                                                        int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
-  const int r = p.r, rp = p.rpad, nb = rp / 16, nt = nb * (nb + 1) / 2;
+  const int r = p.r, rp = p.rpad, nb = rp / 16;
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, li = lane & 15, kg = lane >> 4;
   __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];
-  __shared__ double rpart[(PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2][16];
-  __shared__ double cpart[(PSDPROJ_MAX_RANK / 16) * (PSDPROJ_MAX_RANK / 16 + 1) / 2][16];
+  __shared__ double rpart[TD_NB][TD_NB][16];   // [I][J][row]: C_IJ v_J
+  __shared__ double cpart[TD_NB][16];          // [J][col]: sum over I < J of C_IJ^T v_I
   __shared__ double pvec[PSDPROJ_MAX_RANK];
 
+  // column blocks of this wave: bA = wave, bB = nb-1-wave (bB used only when bB > bA)
+  const int bA = wave, bB = nb - 1 - wave;
+  const bool hasA = bA <= bB;
+  const bool hasB = bA < bB;
+  // slot s: s <= bA -> tile (s, bA); else tile (s - bA - 1, bB)
+  auto slot_ij = [&](int s, int& I, int& J) {
+    if (s <= bA) { I = s; J = bA; }
+    else { I = s - bA - 1; J = bB; }
+  };
+  auto slot_ok = [&](int s) { return s <= bA ? hasA : (hasB && s - bA - 1 <= bB); };
+
   double reg[NS][4];
-  int tI[NS], tJ[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    const int t = wave + s * SYM_WAVES;
-    int I = nb, J = nb;
-    if (t < nt) upper_tile(t, nb, I, J);
-    tI[s] = I;
-    tJ[s] = J;
+    int I, J;
+    slot_ij(s, I, J);
+    const bool ok = slot_ok(s);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int a = 16 * I + li, b = 16 * J + 4 * kg + q;
-      reg[s][q] = (t < nt) ? p.C[(int64_t)b * rp + a] : 0.0;
+      reg[s][q] = ok ? p.C[(int64_t)b * rp + a] : 0.0;
     }
   }
 
   for (int j = 0; j + 2 < r; ++j) {
     double* buf = rowbuf[j & 1];
     const int jb = j >> 4, ji = j & 15;
-    // 1. publish row j (the 16-column strips of row block jb; entries left of j are not read)
+    // 1. publish row j: slot I = jb of every column block J >= jb (entries left of j unused)
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (tI[s] == jb && tJ[s] < nb && li == ji) {
-        double* dst = buf + 16 * tJ[s] + 4 * kg;
+      int I, J;
+      slot_ij(s, I, J);
+      if (slot_ok(s) && I == jb && li == ji) {
+        double* dst = buf + 16 * J + 4 * kg;
         *(double2*)dst = double2{reg[s][0], reg[s][1]};
         *(double2*)(dst + 2) = double2{reg[s][2], reg[s][3]};
       }
@@ -75,121 +115,120 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
       p.te[j] = beta;
       p.tau[j] = tau;
     }
-    for (int i = j + 2 + tid; i < r; i += SYM_THREADS) p.H[(int64_t)j * rp + i] = buf[i] * sc;
-    if (tau != 0.0) {
-      // v_i: 0 (i <= j), 1 (i = j+1), buf[i] * sc (i >= j+2)
-      // 3a. per-tile partial sums of C2 v (rows) and of C2^T v over the tile's rows (columns)
+    for (int i = j + 2 + tid; i < r; i += TD_THREADS) p.H[(int64_t)j * rp + i] = buf[i] * sc;
+    if (tau == 0.0) continue;   // uniform: every wave computed the same tau
+    // v_i: 0 (i <= j), 1 (i = j+1), buf[i] * sc (i >= j+2); padding (>= r) is zero in buf
+    auto vval = [&](int i, double x) { return (i > j + 1) ? x * sc : (i == j + 1 ? 1.0 : 0.0); };
+
+    // 3a. row sums per tile -> rpart; column sums per column block -> cpart
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const int J = blk ? bB : bA;
+      const bool have = blk ? hasB : hasA;
+      if (!have || 16 * J + 15 <= j) continue;   // uniform: no trailing columns in this block
+      const int b0 = 16 * J + 4 * kg;
+      const double2 x01 = *(const double2*)(buf + b0);
+      const double2 x23 = *(const double2*)(buf + b0 + 2);
+      const double vb[4] = {vval(b0, x01.x), vval(b0 + 1, x01.y), vval(b0 + 2, x23.x), vval(b0 + 3, x23.y)};
+      double cs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (tJ[s] >= nb || 16 * tJ[s] + 15 <= j) continue;   // (uniform) no trailing columns here
-        const int t = wave + s * SYM_WAVES;
-        const int a = 16 * tI[s] + li;
-        const int b0 = 16 * tJ[s] + 4 * kg;
-        const double2 x01 = *(const double2*)(buf + b0);
-        const double2 x23 = *(const double2*)(buf + b0 + 2);
-        const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
-        // v restricted to the trailing block; padding (>= r) is zero in buf and in the registers
-        const double va = (a > j + 1) ? buf[a] * sc : (a == j + 1 ? 1.0 : 0.0);
-        const double ma = (a > j) ? 1.0 : 0.0;
-        double rs = 0.0, cs[4];
+        int I, JJ;
+        slot_ij(s, I, JJ);
+        if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;   // compile-time slot, uniform block
+        if (16 * I + 15 <= j) continue;                          // uniform: rows all above the block
+        const int a = 16 * I + li;
+        const double va = vval(a, buf[a]);
+        const bool ra = a > j;
+        double rs = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int b = b0 + q;
-          const double vb = (b > j + 1) ? xb[q] * sc : (b == j + 1 ? 1.0 : 0.0);
-          const double x = (b > j) ? reg[s][q] * ma : 0.0;
-          rs += x * vb;
-          cs[q] = x * va;
+          const double x = (ra && b0 + q > j) ? reg[s][q] : 0.0;
+          rs += x * vb[q];
+          if (I != J) cs[q] += x * va;
         }
-        // row sums: add over the 4 lane groups holding the same row
         rs += __shfl_xor(rs, 16, 64);
         rs += __shfl_xor(rs, 32, 64);
-        if (kg == 0) rpart[t][li] = rs;
-        if (tI[s] != tJ[s]) {
-          // column sums: add over the 16 rows of the tile
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double c = cs[q];
-            c += __shfl_xor(c, 1, 64);
-            c += __shfl_xor(c, 2, 64);
-            c += __shfl_xor(c, 4, 64);
-            c += __shfl_xor(c, 8, 64);
-            if (li == 0) cpart[t][4 * kg + q] = c;
-          }
-        }
+        if (kg == 0) rpart[I][J][li] = rs;
       }
-      __syncthreads();
-      // 3b. p_i = tau * (sum over tiles of row block i/16 + transposed tiles of column block i/16)
-      for (int i = r + tid; i < rp; i += SYM_THREADS) pvec[i] = 0.0;   // padding stays zero
-      for (int i = j + 1 + tid; i < r; i += SYM_THREADS) {
+      colsum16(cs, lane);
+      if ((li & 3) == 0) cpart[J][4 * kg + (li >> 2)] = cs[0];
+    }
+    __syncthreads();
+    // 3b. p_i = tau * (sum_{J >= i/16} C_{i/16,J} v_J + sum_{I < i/16} C_{I,i/16}^T v_I)
+    for (int i = tid; i < rp; i += TD_THREADS) {
+      double s = 0.0;
+      if (i > j && i < r) {
         const int ib = i >> 4, ii = i & 15;
-        double s = 0.0;
-        // tiles (ib, J) for J >= ib: tile index of (ib, J)
-        const int trow = ib * nb - ib * (ib - 1) / 2;   // index of (ib, ib)
-        for (int J = ib; J < nb; ++J) {
-          if (16 * J + 15 <= j) continue;
-          s += rpart[trow + (J - ib)][ii];
+#pragma unroll
+        for (int J = 0; J < TD_NB; ++J) {
+          const double t = (J >= ib && J < nb) ? rpart[ib][J][ii] : 0.0;
+          s += t;
         }
-        for (int I = 0; I < ib; ++I) {
-          if (16 * ib + 15 <= j) continue;
-          const int tix = I * nb - I * (I - 1) / 2 + (ib - I);
-          s += cpart[tix][ii];
-        }
-        pvec[i] = tau * s;
+        s += cpart[ib][ii];
+        s *= tau;
       }
-      __syncthreads();
-      // K = tau/2 p^T v (wave reduction, same in every wave)
-      double dp = 0.0;
-      for (int i = j + 1 + lane; i < r; i += WAVE) {
-        const double vi = (i > j + 1) ? buf[i] * sc : 1.0;
-        dp += pvec[i] * vi;
+      pvec[i] = s;   // zero outside the trailing block and in the padding
+    }
+    __syncthreads();
+    // K = tau/2 p^T v (wave reduction, same in every wave)
+    double dp = 0.0;
+    for (int i = j + 1 + lane; i < r; i += WAVE) dp += pvec[i] * vval(i, buf[i]);
+    const double K = 0.5 * tau * wave_sum(dp);
+    // 4. C2 -= v w^T + w v^T, w = p - K v (zero outside the trailing block)
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const int J = blk ? bB : bA;
+      const bool have = blk ? hasB : hasA;
+      if (!have || 16 * J + 15 <= j) continue;
+      const int b0 = 16 * J + 4 * kg;
+      const double2 x01 = *(const double2*)(buf + b0);
+      const double2 x23 = *(const double2*)(buf + b0 + 2);
+      const double2 p01 = *(const double2*)(pvec + b0);
+      const double2 p23 = *(const double2*)(pvec + b0 + 2);
+      const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
+      const double pb[4] = {p01.x, p01.y, p23.x, p23.y};
+      double vb[4], wb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        vb[q] = vval(b0 + q, xb[q]);
+        wb[q] = pb[q] - K * vb[q];   // pvec is zero for b <= j
       }
-      const double K = 0.5 * tau * wave_sum(dp);
-      // 4. C2 -= v w^T + w v^T, w = p - K v
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (tJ[s] >= nb || 16 * tJ[s] + 15 <= j) continue;
-        const int a = 16 * tI[s] + li;
-        const int b0 = 16 * tJ[s] + 4 * kg;
-        const double2 x01 = *(const double2*)(buf + b0);
-        const double2 x23 = *(const double2*)(buf + b0 + 2);
-        const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
-        const double2 p01 = *(const double2*)(pvec + b0);
-        const double2 p23 = *(const double2*)(pvec + b0 + 2);
-        const double pb[4] = {p01.x, p01.y, p23.x, p23.y};
-        // rows/columns outside the trailing block get zero v and w (no update there)
-        const double va = (a > j + 1) ? buf[a] * sc : (a == j + 1 ? 1.0 : 0.0);
-        const double wa = (a > j) ? pvec[a] - K * va : 0.0;
+        int I, JJ;
+        slot_ij(s, I, JJ);
+        if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;
+        if (16 * I + 15 <= j) continue;
+        const int a = 16 * I + li;
+        const double va = vval(a, buf[a]);
+        const double wa = pvec[a] - K * va;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int b = b0 + q;
-          const double vb = (b > j + 1) ? xb[q] * sc : (b == j + 1 ? 1.0 : 0.0);
-          const double wb = (b > j) ? pb[q] - K * vb : 0.0;
-          reg[s][q] -= va * wb + wa * vb;
-        }
+        for (int q = 0; q < 4; ++q) reg[s][q] -= va * wb[q] + wa * vb[q];
       }
     }
-    // rows >= j+1 of the registers are consistent for the next step; the rpart/cpart/pvec
-    // buffers are rewritten only after the next step's first barrier.
+    // rows >= j+1 of the registers are consistent for the next step; rpart/cpart/pvec are
+    // rewritten only after the next step's first barrier.
   }
   // last 2x2 (or 1x1) block
   if (r >= 2) {
     const int j = r - 2;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      if (tI[s] >= nb) continue;
-      const int a = 16 * tI[s] + li;
+      if (!slot_ok(s)) continue;
+      int I, J;
+      slot_ij(s, I, J);
+      const int a = 16 * I + li;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int b = 16 * tJ[s] + 4 * kg + q;
+        const int b = 16 * J + 4 * kg + q;
         if (a == j && b == j) p.td[j] = reg[s][q];
         if (a == j && b == j + 1) p.te[j] = reg[s][q];
         if (a == j + 1 && b == j + 1) p.td[j + 1] = reg[s][q];
       }
     }
   } else {
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (tI[s] == 0 && tJ[s] == 0 && li == 0 && kg == 0) p.td[0] = reg[s][0];
+    if (wave == 0 && li == 0 && kg == 0) p.td[0] = reg[0][0];
   }
   if (tid == 0) {
     if (r >= 2) p.tau[r - 2] = 0.0;
@@ -227,9 +266,9 @@ __global__ __launch_bounds__(SYM_THREADS) void k_tridiag(const Prob* __restrict_
 
 void launch_tridiag(const Launch& L) {
   if (L.maxnb <= 14)
-    hipLaunchKernelGGL(k_tridiag<14>, dim3(L.grid), dim3(SYM_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+    hipLaunchKernelGGL(k_tridiag<15>, dim3(L.grid), dim3(TD_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
   else
-    hipLaunchKernelGGL(k_tridiag<17>, dim3(L.grid), dim3(SYM_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+    hipLaunchKernelGGL(k_tridiag<17>, dim3(L.grid), dim3(TD_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
 }
 
 }  // namespace psd
