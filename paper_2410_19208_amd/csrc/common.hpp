@@ -99,6 +99,59 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits for every
+// outstanding global load and store of the wave (a round trip to L2 after a store); loops whose
+// waves exchange data through LDS alone use this one.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Orders this wave's LDS accesses across its lanes (no other wave involved).
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Value of v in lane `src` (a constant or wave-uniform index), as a wave-uniform double.
+__device__ __forceinline__ double bcast_f64(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Cross-lane move of a double by a DPP pattern (two 32-bit DPP moves).  Lanes whose row is
+// masked out by ROWMASK, or whose source lane is invalid, receive 0.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROR4 = 0x124;     // row_ror:4 (within 16-lane rows)
+constexpr int DPP_ROR8 = 0x128;     // row_ror:8 (= lane ^ 8 within a row)
+constexpr int DPP_BCAST15 = 0x142;  // row_bcast:15 (lane 15 of each row to the next row)
+constexpr int DPP_BCAST31 = 0x143;  // row_bcast:31 (lane 31 to rows 2 and 3)
+
+// Sum of a double over the wave with DPP moves (no LDS traffic), returned wave-uniform.  The
+// addition order is fixed: quad sums, row sums (rotations by 4 and 8), then rows 0+1 and 2+3,
+// then (0+1)+(2+3), read from lane 63.
+__device__ __forceinline__ double wave_allsum(double v) {
+  v += dpp_f64<DPP_XOR1>(v);
+  v += dpp_f64<DPP_XOR2>(v);
+  v += dpp_f64<DPP_ROR4>(v);
+  v += dpp_f64<DPP_ROR8>(v);
+  v += dpp_f64<DPP_BCAST15, 0xA>(v);
+  v += dpp_f64<DPP_BCAST31, 0xC>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // Tile t of the upper triangle of an nb x nb grid of 16x16 tiles, enumerated row by row:
 // (0,0), (0,1), ..., (0,nb-1), (1,1), ...
 __device__ __forceinline__ void upper_tile(int t, int nb, int& I, int& J) {

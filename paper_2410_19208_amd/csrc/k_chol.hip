@@ -2,11 +2,12 @@
 //   G = Y^T Y, G = R^T R, Q1 = Y R^-1; then once more on Q1.
 // The range of Q equals the range of Y for any invertible R, which is all the method uses.
 //
-// k_chol (one workgroup of 16 waves per problem): blocked right-looking Cholesky on
-// 16x16 FP64 tiles.  The upper-triangle tiles of G live in registers (tile t in wave t mod 16)
+// k_chol (one workgroup of 8 waves per problem): blocked right-looking Cholesky on
+// 16x16 FP64 tiles.  The upper-triangle tiles of G live in registers (tile t in wave t mod 8)
 // in the result layout of v_mfma_f64_16x16x4f64 (lane l holds rows 4v + l/16,
 // column l%16), which is also that instruction's B-operand layout.  For each block column J:
-//   A. the owner of tile (J,J) factors it in LDS (16 scalar steps) and inverts R_JJ;
+//   A. the owner of tile (J,J) factors it in registers (lane c holds column c; pivots and row
+//      entries broadcast with readlane) and inverts R_JJ the same way;
 //   B. the panel tiles become R_JK = R_JJ^-T W_JK (MFMA; B operand straight from registers);
 //   C. the trailing tiles take W_KL -= R_JK^T R_JL (MFMA; operands from the panel in LDS).
 // A column whose Schur pivot is below tol * (its Gram diagonal) lies in the span of the
@@ -22,11 +23,11 @@
 
 namespace psd {
 
-constexpr int CH_WAVES = 16;
+constexpr int CH_WAVES = 8;
 constexpr int CH_THREADS = CH_WAVES * WAVE;
 constexpr int NBMAX = PSDPROJ_MAX_RANK / 16;
 
-// NS register slots per wave: 7 cover r_pad <= 224 (105 tiles), 9 cover r_pad = 256 (136).
+// NS register slots per wave: 14 cover r_pad <= 224 (105 tiles), 17 cover r_pad = 256 (136).
 template <int NS>
 __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                      int nprob, int round) {
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
       reg[s][v] = (t < nt) ? G[(int64_t)b * rp + a] : 0.0;
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   for (int J = 0; J < nb; ++J) {
     // ---- A: factor the diagonal tile (owner wave), R_JJ and R_JJ^-1 into LDS
@@ -72,59 +73,60 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
       for (int s = 0; s < NS; ++s)
         if (s == sd) dt = reg[s];
-      {
+      // tile -> LDS (result layout), then lane c < 16 takes column c into registers
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dsm[4 * v + kg][li] = dt[v];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        for (int jj = 0; jj < 16; ++jj) {
-          const int j = 16 * J + jj;
-          const double d = dsm[jj][jj], gj = g0[j];
-          const bool dr = !(gj > 0.0) || !(d > tol * gj) || !isfinite(d);
-          const double piv = dr ? 0.0 : sqrt(d);
-          const double ip = dr ? 0.0 : 1.0 / piv;
-          // lanes 0..15 hold the row-jj values of columns c = lane
-          double rowv = 0.0;
-          if (lane < 16) rowv = (lane > jj) ? dsm[jj][lane] * ip : 0.0;
-          __builtin_amdgcn_wave_barrier();
-          // trailing update of the tile: element (a, c), a, c > jj; 4 elements per lane
+      for (int v = 0; v < 4; ++v) dsm[4 * v + kg][li] = dt[v];
+      lds_wave_sync();
+      double col[16];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int a = 4 * e + kg, c = li;
-            const double ua = __shfl(rowv, a, 64), uc = __shfl(rowv, c, 64);
-            if (a > jj && c > jj) dsm[a][c] -= ua * uc;
-          }
-          if (lane < 16) {
-            if (lane > jj) dsm[jj][lane] = rowv;
-            else if (lane == jj) dsm[jj][jj] = dr ? 1.0 : piv;
-          }
-          if (lane == 0) dflag[j] = dr;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-        // R_JJ^-1: lane c < 16 solves R_JJ x = e_c by back substitution
-        if (lane < 16) {
-          const int c = lane;
-          for (int i = 15; i >= 0; --i) {
-            double acc = (i == c) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= c; ++k) acc -= dsm[i][k] * dinv[k][c];
-            dinv[i][c] = (i > c || dflag[16 * J + i]) ? 0.0 : acc / dsm[i][i];
-          }
-        }
-        // R_JJ (upper, zero below) back into the owner's registers
+      for (int a = 0; a < 16; ++a) col[a] = dsm[a][li];   // lanes >= 16 hold copies, unused
+      // right-looking Cholesky of the tile: step jj scales row jj by 1/sqrt(pivot) and updates
+      // the trailing part; pivots and row entries are broadcast with readlane (wave-uniform)
+      int drops = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = 4 * v + kg, c = li;
-          dt[v] = (a <= c) ? dsm[a][c] : 0.0;
-        }
+      for (int jj = 0; jj < 16; ++jj) {
+        const double d = bcast_f64(col[jj], jj);
+        const double gj = g0[16 * J + jj];
+        const bool dr = !(gj > 0.0) || !(d > tol * gj) || !isfinite(d);
+        const double piv = dr ? 0.0 : sqrt(d);
+        const double ip = dr ? 0.0 : 1.0 / piv;
+        const double rowv = (lane > jj) ? col[jj] * ip : 0.0;   // R[jj][c], c = lane
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
-          if (s == sd) reg[s] = dt;
+        for (int a = jj + 1; a < 16; ++a) col[a] -= bcast_f64(rowv, a) * rowv;
+        col[jj] = (lane > jj) ? rowv : (lane == jj ? (dr ? 1.0 : piv) : col[jj]);
+        drops |= (dr ? 1 : 0) << jj;
+        __builtin_amdgcn_sched_barrier(0);   // keep the broadcasts of one step together
       }
+      // R_JJ^-1 (upper triangular): lane c solves R x = e_c by back substitution, with the
+      // entries R[i][k] (column k, lane k) broadcast; dropped rows of the inverse are zero
+      double x[16];
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        double acc = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = i + 1; k < 16; ++k) acc -= bcast_f64(col[i], k) * x[k];
+        const double rii = bcast_f64(col[i], i);
+        x[i] = (i > lane || ((drops >> i) & 1)) ? 0.0 : acc / rii;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // R_JJ (upper, zero below) and its inverse to LDS; R_JJ back to the owner's registers
+      lds_wave_sync();
+      if (lane < 16) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+          dsm[a][lane] = (a <= lane) ? col[a] : 0.0;
+          dinv[a][lane] = x[a];
+        }
+        dflag[16 * J + lane] = (drops >> lane) & 1;
+      }
+      lds_wave_sync();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dt[v] = dsm[4 * v + kg][li];
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s == sd) reg[s] = dt;
     }
-    __syncthreads();
+    lds_barrier();
     if (wave == 0) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
       for (int v = 0; v < 4; ++v) panel[K][4 * v + kg][li] = acc[v];
     }
-    __syncthreads();
+    lds_barrier();
     // ---- C: trailing tiles W_KL -= R_JK^T R_JL, J < K <= L
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
       H[(int64_t)b * rp + a] = reg[s][v];
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (tid == 0) {
     int ndrop = 0;
     for (int j = 0; j < r; ++j) ndrop += dflag[j];
@@ -219,7 +221,7 @@ __device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, do
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) Qw[(4 * v + kg) * qld + 16 * J + li] = acc[v];
-    __syncthreads();
+    lds_wave_sync();   // Qw is this wave's own LDS region
     f64x4 q = {0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -228,7 +230,7 @@ __device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, do
       const double b = Dinv[(int64_t)(16 * J + li) * rp + 16 * J + k];
       q = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, q, 0, 0, 0);
     }
-    __syncthreads();
+    lds_wave_sync();   // Qw is this wave's own LDS region
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = rowbase + 4 * v + kg;
@@ -242,7 +244,7 @@ __device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, do
         p.zlo[o] = (bf16)((float)val - (float)h);
       }
     }
-    __syncthreads();
+    lds_wave_sync();   // Qw is this wave's own LDS region
   }
 }
 
@@ -314,9 +316,9 @@ void apply_init() {
 
 void launch_chol(const Launch& L, int round) {
   if (L.maxnb <= 14)
-    hipLaunchKernelGGL(k_chol<7>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
+    hipLaunchKernelGGL(k_chol<14>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
   else
-    hipLaunchKernelGGL(k_chol<9>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
+    hipLaunchKernelGGL(k_chol<17>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
 }
 void launch_apply(const Launch& L, int round) {
   hipLaunchKernelGGL(k_apply, dim3(L.grid), dim3(AP_THREADS), apply_smem(), L.stream, L.probs, L.tstart, L.nprob,

@@ -3,14 +3,15 @@
 //
 // The upper-triangle 16x16 tiles of the symmetric r_pad x r_pad matrix live in registers.  A
 // wave owns whole column blocks, paired as J and nb-1-J so every wave holds nb+1 tiles; lane l
-// of a tile holds row l%16, columns 4*(l/16) .. +3.  Step j (j = 0 .. r-3):
+// of a tile holds row l/4, columns 4*(l%4) .. +3.  Step j (j = 0 .. r-3):
 //   1. the owners of row j publish it through LDS (double-buffered);
 //   2. every wave forms the reflector H_j = I - tau v v^T that maps C[j+1:, j] to beta e_1
 //      (redundantly, identical arithmetic in every wave, so no extra barrier);
-//   3. p = tau C2 v (C2 = trailing block): per tile, the row sums C_IJ v_J (a 4-lane reduction)
-//      go to LDS; the column sums C_IJ^T v_I accumulate in registers over a column block and
-//      are reduced once per block (16-lane reduce-scatter); p_i adds the nb row-block terms and
-//      the column-block term in a fixed order; K = tau/2 p^T v, w = p - K v;
+//   3. p = tau C2 v (C2 = trailing block): per tile, the row sums C_IJ v_J (a quad reduction
+//      with DPP moves) go to LDS; the column sums C_IJ^T v_I accumulate in registers over a
+//      column block and are reduced once per block (16-lane reduce-scatter); p_i adds the nb
+//      row-block terms and the column-block term in a fixed order; K = tau/2 p^T v,
+//      w = p - K v;
 //   4. C2 -= v w^T + w v^T on the registers.
 // Tiles left of or above the trailing block are skipped (wave-uniform tests).
 // Outputs: diagonal d and off-diagonal e of T, tau_j, the reflector vectors v (entries j+2..r-1)
@@ -25,26 +26,27 @@ constexpr int TD_WAVES = 8;
 constexpr int TD_THREADS = TD_WAVES * WAVE;
 constexpr int TD_NB = PSDPROJ_MAX_RANK / 16;   // 16 column blocks at most
 
-// Sum over the 16 lanes of a row group (lane bits 0..3) of c[0..3]: afterwards lane l holds the
-// full sum of c[(l >> 2) & 3] in c[0].  Halving over bits 3 and 2, then a butterfly over bits 1
-// and 0; fixed order.
+// Column sums of a tile block: c[q] of lane l is a partial sum for column 4*(l%4) + q over the
+// rows held by lane l; the 16 lanes sharing l%4 are added.  Halving over lane bits 5 and 4,
+// then rotations by 4 and 8 within each 16-lane row (bits 3 and 2); afterwards the lanes with
+// bits 2 and 3 clear hold the sum for column 4*(l%4) + ((l >> 4) & 3) in c[0].  Fixed order.
 __device__ __forceinline__ void colsum16(double (&c)[4], int lane) {
   {
-    const bool up = (lane & 8) != 0;
+    const bool up = (lane & 32) != 0;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const double lo = c[k], hi = c[k + 2];
       const double keep = up ? hi : lo, send = up ? lo : hi;
-      c[k] = keep + __shfl_xor(send, 8, 64);
+      c[k] = keep + __shfl_xor(send, 32, 64);
     }
   }
   {
-    const bool up = (lane & 4) != 0;
+    const bool up = (lane & 16) != 0;
     const double keep = up ? c[1] : c[0], send = up ? c[0] : c[1];
-    c[0] = keep + __shfl_xor(send, 4, 64);
+    c[0] = keep + __shfl_xor(send, 16, 64);
   }
-  c[0] += __shfl_xor(c[0], 2, 64);
-  c[0] += __shfl_xor(c[0], 1, 64);
+  c[0] += dpp_f64<DPP_ROR4>(c[0]);
+  c[0] += dpp_f64<DPP_ROR8>(c[0]);
 }
 
 template <int NS>   // register slots per wave: nb + 1 (15: r_pad <= 224, 17: r_pad = 256)
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int r = p.r, rp = p.rpad, nb = rp / 16;
-  const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, li = lane & 15, kg = lane >> 4;
+  const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, lr = lane >> 2, lc = lane & 3;
   __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];
   __shared__ double rpart[TD_NB][TD_NB][16];   // [I][J][row]: C_IJ v_J
   __shared__ double cpart[TD_NB][16];          // [J][col]: sum over I < J of C_IJ^T v_I
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     const bool ok = slot_ok(s);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int a = 16 * I + li, b = 16 * J + 4 * kg + q;
+      const int a = 16 * I + lr, b = 16 * J + 4 * lc + q;
       reg[s][q] = ok ? p.C[(int64_t)b * rp + a] : 0.0;
     }
   }
@@ -91,17 +93,17 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     for (int s = 0; s < NS; ++s) {
       int I, J;
       slot_ij(s, I, J);
-      if (slot_ok(s) && I == jb && li == ji) {
-        double* dst = buf + 16 * J + 4 * kg;
+      if (slot_ok(s) && I == jb && lr == ji) {
+        double* dst = buf + 16 * J + 4 * lc;
         *(double2*)dst = double2{reg[s][0], reg[s][1]};
         *(double2*)(dst + 2) = double2{reg[s][2], reg[s][3]};
       }
     }
-    __syncthreads();
+    lds_barrier();
     // 2. reflector: x = buf[j+1 ..], sigma = ||x[1:]||^2 (wave reduction, same in every wave)
     double part = 0.0;
     for (int i = j + 2 + lane; i < r; i += WAVE) part += buf[i] * buf[i];
-    const double sigma = wave_sum(part);
+    const double sigma = wave_allsum(part);
     const double alpha = buf[j + 1];
     double tau = 0.0, beta = alpha, sc = 0.0;
     if (sigma > 0.0) {
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
       const int J = blk ? bB : bA;
       const bool have = blk ? hasB : hasA;
       if (!have || 16 * J + 15 <= j) continue;   // uniform: no trailing columns in this block
-      const int b0 = 16 * J + 4 * kg;
+      const int b0 = 16 * J + 4 * lc;
       const double2 x01 = *(const double2*)(buf + b0);
       const double2 x23 = *(const double2*)(buf + b0 + 2);
       const double vb[4] = {vval(b0, x01.x), vval(b0 + 1, x01.y), vval(b0 + 2, x23.x), vval(b0 + 3, x23.y)};
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
         slot_ij(s, I, JJ);
         if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;   // compile-time slot, uniform block
         if (16 * I + 15 <= j) continue;                          // uniform: rows all above the block
-        const int a = 16 * I + li;
+        const int a = 16 * I + lr;
         const double va = vval(a, buf[a]);
         const bool ra = a > j;
         double rs = 0.0;
@@ -147,14 +149,14 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
           rs += x * vb[q];
           if (I != J) cs[q] += x * va;
         }
-        rs += __shfl_xor(rs, 16, 64);
-        rs += __shfl_xor(rs, 32, 64);
-        if (kg == 0) rpart[I][J][li] = rs;
+        rs += dpp_f64<DPP_XOR1>(rs);
+        rs += dpp_f64<DPP_XOR2>(rs);
+        if (lc == 0) rpart[I][J][lr] = rs;
       }
       colsum16(cs, lane);
-      if ((li & 3) == 0) cpart[J][4 * kg + (li >> 2)] = cs[0];
+      if ((lane & 12) == 0) cpart[J][4 * lc + ((lane >> 4) & 3)] = cs[0];
     }
-    __syncthreads();
+    lds_barrier();
     // 3b. p_i = tau * (sum_{J >= i/16} C_{i/16,J} v_J + sum_{I < i/16} C_{I,i/16}^T v_I)
     for (int i = tid; i < rp; i += TD_THREADS) {
       double s = 0.0;
@@ -162,26 +164,26 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
         const int ib = i >> 4, ii = i & 15;
 #pragma unroll
         for (int J = 0; J < TD_NB; ++J) {
-          const double t = (J >= ib && J < nb) ? rpart[ib][J][ii] : 0.0;
-          s += t;
+          const double t = rpart[ib][J][ii];   // in bounds for every J; stale entries are not added
+          s += (J >= ib && J < nb) ? t : 0.0;
         }
         s += cpart[ib][ii];
         s *= tau;
       }
       pvec[i] = s;   // zero outside the trailing block and in the padding
     }
-    __syncthreads();
+    lds_barrier();
     // K = tau/2 p^T v (wave reduction, same in every wave)
     double dp = 0.0;
     for (int i = j + 1 + lane; i < r; i += WAVE) dp += pvec[i] * vval(i, buf[i]);
-    const double K = 0.5 * tau * wave_sum(dp);
+    const double K = 0.5 * tau * wave_allsum(dp);
     // 4. C2 -= v w^T + w v^T, w = p - K v (zero outside the trailing block)
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
       const int J = blk ? bB : bA;
       const bool have = blk ? hasB : hasA;
       if (!have || 16 * J + 15 <= j) continue;
-      const int b0 = 16 * J + 4 * kg;
+      const int b0 = 16 * J + 4 * lc;
       const double2 x01 = *(const double2*)(buf + b0);
       const double2 x23 = *(const double2*)(buf + b0 + 2);
       const double2 p01 = *(const double2*)(pvec + b0);
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
         slot_ij(s, I, JJ);
         if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;
         if (16 * I + 15 <= j) continue;
-        const int a = 16 * I + li;
+        const int a = 16 * I + lr;
         const double va = vval(a, buf[a]);
         const double wa = pvec[a] - K * va;
 #pragma unroll
@@ -218,17 +220,17 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
       if (!slot_ok(s)) continue;
       int I, J;
       slot_ij(s, I, J);
-      const int a = 16 * I + li;
+      const int a = 16 * I + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int b = 16 * J + 4 * kg + q;
+        const int b = 16 * J + 4 * lc + q;
         if (a == j && b == j) p.td[j] = reg[s][q];
         if (a == j && b == j + 1) p.te[j] = reg[s][q];
         if (a == j + 1 && b == j + 1) p.td[j + 1] = reg[s][q];
       }
     }
   } else {
-    if (wave == 0 && li == 0 && kg == 0) p.td[0] = reg[0][0];
+    if (wave == 0 && lane == 0) p.td[0] = reg[0][0];
   }
   if (tid == 0) {
     if (r >= 2) p.tau[r - 2] = 0.0;
