@@ -23,8 +23,10 @@
  *   X ("A" below), P, the workspace and result_dev are caller-owned DEVICE memory on the
  *   current HIP device.  Plans and servers are library-owned opaque handles.  A must stay
  *   valid and unchanged until the stream has passed the call (or the ticket completed).
- *   A is read in full and must be exactly symmetric.  Row- and column-major are the same
- *   for a symmetric matrix; element (i, j) is at A[i * lda + j].
+ *   A must be exactly symmetric (the method projects a symmetric matrix, Sec. 2).  The passes
+ *   of Alg. 1-3 read it in full; the power iterations of Alg. 4/5 read only its upper
+ *   triangle and diagonal.  Row- and column-major are the same for a symmetric matrix;
+ *   element (i, j) is at A[i * lda + j].
  *   Precision FP64: A and P hold double.  FP32 and BF16X3: A and P hold float.
  *   Requirements: lda >= n, ldp >= n, A and P 16-byte aligned.  When lda * sizeof(element)
  *   is a multiple of 16 the passes over A use 16-byte vector loads; otherwise they fall back
