@@ -153,16 +153,23 @@ psdproj_status psdproj_batch(int32_t count, const psdproj_plan_t* plans, const v
                              const int64_t* lda, void* const* P, const int64_t* ldp, void* workspace,
                              size_t workspace_bytes, psdproj_result* results_dev, psdproj_stream_t stream);
 
-/* Continuous-batching request server on the current device.  Requests are admitted while
- * the sum of their workspace footprints stays within hbm_budget_bytes and fewer than
- * max_inflight are in flight; admitted requests advance together, one grouped stage at a
- * time, and new arrivals join at the next stage boundary.  A and P stay caller-owned. */
+/* Continuous-batching request server on the current device (the batching of many independent
+ * projections, each one Alg. 1 + Alg. 2 or Alg. 3).  hbm_budget_bytes of device memory is
+ * allocated at creation and holds the workspaces of the requests in flight.  Requests are
+ * admitted in FIFO order while their workspaces fit in it and fewer than max_inflight are in
+ * flight; each admission round becomes one grouped launch sequence (as psdproj_batch) on one
+ * of two server streams, and arrivals join at the next round.  A and P stay caller-owned and
+ * must stay valid until the ticket completes.  Each request's P is bitwise identical to a
+ * psdproj_run of the same desc.  submit validates synchronously (E_INVALID; E_BUDGET when the
+ * request alone exceeds the budget); a device failure of a batch is reported in the status
+ * of each of its requests.  All server functions are thread-safe. */
 psdproj_status psdproj_server_create(size_t hbm_budget_bytes, int32_t max_inflight, psdproj_server_t* out);
 psdproj_status psdproj_submit(psdproj_server_t server, const psdproj_desc* desc, const void* A, int64_t lda,
                               void* P, int64_t ldp, uint64_t* ticket);
 /* E_PENDING while in flight; otherwise copies the result to *out (host memory), returns
  * PSDPROJ_OK, and forgets the ticket. */
 psdproj_status psdproj_poll(psdproj_server_t server, uint64_t ticket, psdproj_result* out);
+/* Blocks until the ticket completes (timeout_s < 0: no limit); E_TIMEOUT keeps the ticket. */
 psdproj_status psdproj_wait(psdproj_server_t server, uint64_t ticket, psdproj_result* out, double timeout_s);
 /* Per-request timestamps in seconds since server creation: submit, admit, finish. */
 psdproj_status psdproj_server_times(psdproj_server_t server, uint64_t ticket, double* t_submit,

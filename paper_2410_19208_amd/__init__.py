@@ -54,7 +54,7 @@ class PsdprojError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_19208_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2410_19208_amd/build.py` "
                       "(the projection has no non-HIP path)")
 try:
     # PyTorch bundles its own HIP runtime under the same soname; load it first so that the

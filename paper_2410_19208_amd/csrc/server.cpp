@@ -1,10 +1,365 @@
-// Placeholder request server (replaced by the continuous-batching server).
-#include "psdproj.h"
-extern "C" {
-psdproj_status psdproj_server_create(size_t, int32_t, psdproj_server_t* out) { if (out) *out = nullptr; return PSDPROJ_E_INVALID; }
-psdproj_status psdproj_submit(psdproj_server_t, const psdproj_desc*, const void*, int64_t, void*, int64_t, uint64_t*) { return PSDPROJ_E_INVALID; }
-psdproj_status psdproj_poll(psdproj_server_t, uint64_t, psdproj_result*) { return PSDPROJ_E_INVALID; }
-psdproj_status psdproj_wait(psdproj_server_t, uint64_t, psdproj_result*, double) { return PSDPROJ_E_INVALID; }
-psdproj_status psdproj_server_times(psdproj_server_t, uint64_t, double*, double*, double*) { return PSDPROJ_E_INVALID; }
-void psdproj_server_destroy(psdproj_server_t) {}
+// Continuous-batching request server (psdproj_server_* of psdproj.h).
+//
+// A worker thread owns two HIP streams and one device pool of hbm_budget_bytes, carved by a
+// first-fit allocator.  Requests are admitted in FIFO order while their workspace fits in the
+// pool and fewer than max_inflight are in flight; every admission round puts the admitted
+// requests into one grouped launch sequence (run_group, the engine of psdproj_batch) on the
+// stream that is free, so two batches can overlap on the GPU (the single-workgroup stages of
+// one batch leave most CUs to the other).  Completion is seen through an event; the batch's
+// device result records come back through pinned host memory.  A request gets exactly the
+// tiling it would get alone, so its P is bitwise identical to a psdproj_run of the same desc.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace psd {
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Req {
+  uint64_t ticket = 0;
+  Plan plan;
+  const void* A = nullptr;
+  int64_t lda = 0;
+  void* P = nullptr;
+  int64_t ldp = 0;
+  bool done = false;
+  psdproj_result res{};
+};
+
+struct Times { double submit = -1, admit = -1, finish = -1; };
+
+// First-fit allocator over [0, size) with 256-byte granularity.
+class Pool {
+ public:
+  void reset(size_t size) { free_.clear(); free_[0] = size; }
+  bool alloc(size_t bytes, size_t& off) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        off = it->first;
+        const size_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;   // offset -> length
+};
+
+struct Batch {
+  std::vector<std::shared_ptr<Req>> reqs;
+  size_t off = 0, bytes = 0;
+  int stream = 0;
+  hipEvent_t done = nullptr;
+  psdproj_result* host = nullptr;   // the stream's pinned result records
+};
+
+constexpr int NSTREAMS = 2;
+
+}  // namespace
+
+struct Server {
+  int device = 0;
+  size_t budget = 0;
+  int max_inflight = 1;
+  unsigned char* pool_dev = nullptr;
+  Pool pool;
+  hipStream_t streams[NSTREAMS] = {};
+  psdproj_result* host_res[NSTREAMS] = {};   // pinned, max_inflight records per stream
+  bool stream_busy[NSTREAMS] = {};
+  clk::time_point t0;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Req>> pending;
+  std::map<uint64_t, std::shared_ptr<Req>> live;   // submitted, not yet collected
+  std::vector<Times> times;                        // index: ticket - 1
+  std::vector<Batch> running;
+  int inflight = 0;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+
+  double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
+
+  void loop();
+  bool try_launch(std::unique_lock<std::mutex>& lk);
+  void reap(std::unique_lock<std::mutex>& lk);
+};
+
+// Admit the longest FIFO prefix of pending that fits, and launch it as one batch.
+bool Server::try_launch(std::unique_lock<std::mutex>& lk) {
+  int sidx = -1;
+  for (int i = 0; i < NSTREAMS; ++i)
+    if (!stream_busy[i]) { sidx = i; break; }
+  if (sidx < 0 || pending.empty() || inflight >= max_inflight) return false;
+  std::vector<std::shared_ptr<Req>> take;
+  std::vector<const Plan*> plans;
+  size_t need = 0, off = 0;
+  while (!pending.empty() && inflight + (int)take.size() < max_inflight) {
+    plans.push_back(&pending.front()->plan);
+    Schedule s;
+    build_schedule(plans.data(), (int)plans.size(), s);
+    size_t b = s.header_bytes + (size_t)plans.size() * sizeof(psdproj_result) + 256;
+    for (const Plan* p : plans) b += p->region;
+    size_t trial = 0;
+    if (!pool.alloc(b, trial)) { plans.pop_back(); break; }
+    pool.release(trial, b);
+    need = b;
+    take.push_back(pending.front());
+    pending.pop_front();
+  }
+  if (take.empty()) return false;
+  if (!pool.alloc(need, off)) {   // cannot happen (checked above); put the requests back
+    for (auto it = take.rbegin(); it != take.rend(); ++it) pending.push_front(*it);
+    return false;
+  }
+  Batch bt;
+  bt.reqs = take;
+  bt.off = off;
+  bt.bytes = need;
+  bt.stream = sidx;
+  const int count = (int)take.size();
+  const double ta = now();
+  for (auto& r : take) times[r->ticket - 1].admit = ta;
+  inflight += count;
+  stream_busy[sidx] = true;
+  lk.unlock();
+
+  // results at the end of the allocation, workspace (256-byte aligned) at its start
+  unsigned char* base = pool_dev + off;
+  const size_t res_off = (need - (size_t)count * sizeof(psdproj_result) - 255) & ~(size_t)255;
+  psdproj_result* res_dev = (psdproj_result*)(base + res_off);
+  std::vector<const void*> A(count);
+  std::vector<int64_t> lda(count), ldp(count);
+  std::vector<void*> P(count);
+  for (int i = 0; i < count; ++i) {
+    A[i] = take[i]->A; lda[i] = take[i]->lda; P[i] = take[i]->P; ldp[i] = take[i]->ldp;
+  }
+  bt.host = host_res[sidx];
+  psdproj_status st = run_group(count, plans.data(), A.data(), lda.data(), P.data(), ldp.data(), base, res_off, res_dev,
+                   streams[sidx]);
+  if (st == PSDPROJ_OK &&
+      hipMemcpyAsync(bt.host, res_dev, (size_t)count * sizeof(psdproj_result), hipMemcpyDeviceToHost,
+                     streams[sidx]) != hipSuccess)
+    st = PSDPROJ_E_DEVICE;
+  if (st == PSDPROJ_OK && (hipEventCreateWithFlags(&bt.done, hipEventDisableTiming) != hipSuccess ||
+                           hipEventRecord(bt.done, streams[sidx]) != hipSuccess))
+    st = PSDPROJ_E_DEVICE;
+  if (st != PSDPROJ_OK) {
+    // the batch never ran: every request finishes with the error (after the stream drains,
+    // so the pool region is not reused under a partially enqueued sequence)
+    hipStreamSynchronize(streams[sidx]);
+    if (bt.done) hipEventDestroy(bt.done);
+    bt.done = nullptr;
+  }
+  lk.lock();
+  if (st != PSDPROJ_OK) {
+    const double tf = now();
+    for (auto& r : take) {
+      r->res = psdproj_result{};
+      r->res.status = st;
+      r->done = true;
+      times[r->ticket - 1].finish = tf;
+    }
+    pool.release(off, need);
+    inflight -= count;
+    stream_busy[sidx] = false;
+    cv_done.notify_all();
+    return true;
+  }
+  running.push_back(bt);
+  return true;
 }
+
+// Collect every finished batch.
+void Server::reap(std::unique_lock<std::mutex>& lk) {
+  (void)lk;
+  for (size_t i = 0; i < running.size();) {
+    Batch& bt = running[i];
+    if (hipEventQuery(bt.done) != hipSuccess) { ++i; continue; }
+    const double tf = now();
+    for (size_t k = 0; k < bt.reqs.size(); ++k) {
+      bt.reqs[k]->res = bt.host[k];
+      bt.reqs[k]->done = true;
+      times[bt.reqs[k]->ticket - 1].finish = tf;
+    }
+    hipEventDestroy(bt.done);
+    pool.release(bt.off, bt.bytes);
+    inflight -= (int)bt.reqs.size();
+    stream_busy[bt.stream] = false;
+    running.erase(running.begin() + i);
+    cv_done.notify_all();
+  }
+}
+
+void Server::loop() {
+  hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    reap(lk);
+    while (try_launch(lk)) {}
+    if (stop && pending.empty() && running.empty()) break;
+    // sleep until new work arrives, or poll the running batches' events
+    if (running.empty()) cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+    else cv_work.wait_for(lk, std::chrono::microseconds(50));
+  }
+}
+
+}  // namespace psd
+
+using psd::Server;
+
+extern "C" {
+
+psdproj_status psdproj_server_create(size_t hbm_budget_bytes, int32_t max_inflight, psdproj_server_t* out) {
+  if (!out) return PSDPROJ_E_INVALID;
+  *out = nullptr;
+  if (hbm_budget_bytes < 4096 || max_inflight < 1) return PSDPROJ_E_INVALID;
+  auto* s = new Server();
+  s->budget = (hbm_budget_bytes + 255) & ~(size_t)255;
+  s->max_inflight = max_inflight;
+  if (hipGetDevice(&s->device) != hipSuccess) { delete s; return PSDPROJ_E_DEVICE; }
+  if (hipMalloc((void**)&s->pool_dev, s->budget) != hipSuccess) { delete s; return PSDPROJ_E_NOMEM; }
+  for (int i = 0; i < psd::NSTREAMS; ++i) {
+    if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void**)&s->host_res[i], (size_t)max_inflight * sizeof(psdproj_result),
+                      hipHostMallocDefault) != hipSuccess) {
+      for (int j = 0; j <= i; ++j) {
+        if (s->streams[j]) hipStreamDestroy(s->streams[j]);
+        if (s->host_res[j]) hipHostFree(s->host_res[j]);
+      }
+      hipFree(s->pool_dev);
+      delete s;
+      return PSDPROJ_E_DEVICE;
+    }
+  }
+  s->pool.reset(s->budget);
+  s->t0 = psd::clk::now();
+  s->worker = std::thread([s] { s->loop(); });
+  *out = (psdproj_server_t)s;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_submit(psdproj_server_t server, const psdproj_desc* desc, const void* A, int64_t lda,
+                              void* P, int64_t ldp, uint64_t* ticket) {
+  Server* s = (Server*)server;
+  if (!s || !desc || !ticket) return PSDPROJ_E_INVALID;
+  auto r = std::make_shared<psd::Req>();
+  psdproj_status st = psd::make_plan(desc, r->plan);
+  if (st != PSDPROJ_OK) return st;
+  st = psd::check_operands(r->plan, A, lda, P, ldp);
+  if (st != PSDPROJ_OK) return st;
+  {
+    // a request that could never be admitted alone is refused now
+    const psd::Plan* one = &r->plan;
+    psd::Schedule sc;
+    psd::build_schedule(&one, 1, sc);
+    const size_t need = sc.header_bytes + r->plan.region + sizeof(psdproj_result) + 512;
+    if (need > s->budget) return PSDPROJ_E_BUDGET;
+  }
+  r->A = A; r->lda = lda; r->P = P; r->ldp = ldp;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) return PSDPROJ_E_INVALID;
+    r->ticket = s->next_ticket++;
+    s->times.push_back(psd::Times{s->now(), -1, -1});
+    s->live[r->ticket] = r;
+    s->pending.push_back(r);
+  }
+  s->cv_work.notify_one();
+  *ticket = r->ticket;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_poll(psdproj_server_t server, uint64_t ticket, psdproj_result* out) {
+  Server* s = (Server*)server;
+  if (!s) return PSDPROJ_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->live.find(ticket);
+  if (it == s->live.end()) return PSDPROJ_E_INVALID;
+  if (!it->second->done) return PSDPROJ_E_PENDING;
+  if (out) *out = it->second->res;
+  s->live.erase(it);
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_wait(psdproj_server_t server, uint64_t ticket, psdproj_result* out, double timeout_s) {
+  Server* s = (Server*)server;
+  if (!s) return PSDPROJ_E_INVALID;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->live.find(ticket);
+  if (it == s->live.end()) return PSDPROJ_E_INVALID;
+  std::shared_ptr<psd::Req> r = it->second;
+  auto ready = [&] { return r->done; };
+  if (timeout_s < 0) s->cv_done.wait(lk, ready);
+  else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) return PSDPROJ_E_TIMEOUT;
+  if (out) *out = r->res;
+  s->live.erase(ticket);
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_server_times(psdproj_server_t server, uint64_t ticket, double* t_submit, double* t_admit,
+                                    double* t_finish) {
+  Server* s = (Server*)server;
+  if (!s) return PSDPROJ_E_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (ticket < 1 || ticket > s->times.size()) return PSDPROJ_E_INVALID;
+  const psd::Times& t = s->times[ticket - 1];
+  if (t_submit) *t_submit = t.submit;
+  if (t_admit) *t_admit = t.admit;
+  if (t_finish) *t_finish = t.finish;
+  return PSDPROJ_OK;
+}
+
+void psdproj_server_destroy(psdproj_server_t server) {
+  Server* s = (Server*)server;
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();   // drains pending and running batches
+  for (int i = 0; i < psd::NSTREAMS; ++i) {
+    hipStreamDestroy(s->streams[i]);
+    hipHostFree(s->host_res[i]);
+  }
+  hipFree(s->pool_dev);
+  delete s;
+}
+
+}  // extern "C"

@@ -10,9 +10,10 @@ import ctypes
 import torch
 
 from . import (BF16X3, FP32, FP64, PLAIN, SCALED, Layout, Result, psdproj_batch, psdproj_batch_workspace,
-               psdproj_plan, psdproj_plan_destroy, psdproj_plan_layout, psdproj_run)
+               psdproj_plan, psdproj_plan_destroy, psdproj_plan_layout, psdproj_poll, psdproj_run,
+               psdproj_server_create, psdproj_server_destroy, psdproj_server_times, psdproj_submit, psdproj_wait)
 
-__all__ = ["Projector", "BatchProjector", "stream_handle", "read_results", "PRECISIONS", "VARIANTS",
+__all__ = ["Projector", "BatchProjector", "Server", "stream_handle", "read_results", "PRECISIONS", "VARIANTS",
            "storage_dtype"]
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
@@ -146,3 +147,58 @@ class BatchProjector:
 
     def results(self):
         return read_results(self.result_buf, len(self.plans))
+
+
+class Server:
+    """The continuous-batching request server (psdproj_server_*).
+
+    submit() takes a device tensor A (and optionally the output P), synchronises the current
+    stream so that A is complete before the server's own streams read it, and returns a
+    ticket; wait()/poll() return the device-written result record.  The tensors are kept
+    alive until their ticket is collected.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 64, device="cuda"):
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.handle = psdproj_server_create(int(hbm_budget_bytes), int(max_inflight))
+        self._keep = {}
+
+    def submit(self, A: torch.Tensor, k: int, p: int, q: int = 0, variant="plain", precision="bf16x3", seed=0,
+               alpha=0.0, alpha_iters=10, P: torch.Tensor | None = None):
+        vv = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        pp = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        n = A.shape[0]
+        if A.dtype != storage_dtype(pp) or A.device != self.device or A.shape != (n, n) or A.stride(1) != 1:
+            raise ValueError(f"A must be a row-contiguous {n}x{n} {storage_dtype(pp)} tensor on {self.device}")
+        if P is None:
+            P = torch.empty_like(A)
+        torch.cuda.current_stream(self.device).synchronize()
+        t = psdproj_submit(self.handle, A.data_ptr(), A.stride(0), P.data_ptr(), P.stride(0), n, k, p, q, vv, pp,
+                           seed, alpha, alpha_iters)
+        self._keep[t] = (A, P)
+        return t, P
+
+    def poll(self, ticket):
+        r = psdproj_poll(self.handle, ticket)
+        if r is not None:
+            self._keep.pop(ticket, None)
+        return r
+
+    def wait(self, ticket, timeout_s: float = -1.0):
+        r = psdproj_wait(self.handle, ticket, timeout_s)
+        self._keep.pop(ticket, None)
+        return r
+
+    def times(self, ticket):
+        """(submit, admit, finish) in seconds since the server was created."""
+        return psdproj_server_times(self.handle, ticket)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            psdproj_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()

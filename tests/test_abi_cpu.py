@@ -143,3 +143,15 @@ def test_status_strings():
     for s in range(10):
         assert isinstance(pp.psdproj_status_str(s), str) and pp.psdproj_status_str(s)
     assert pp.psdproj_status_str(0) == "ok"
+
+
+def test_server_create_without_device_fails_cleanly():
+    """On a host without a GPU the server reports an error status instead of crashing."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_2410_19208_amd as pp
+    with pytest.raises(pp.PsdprojError):
+        pp.psdproj_server_create(1 << 20, 4)
+    with pytest.raises(pp.PsdprojError):
+        pp.psdproj_server_create(16, 4)   # budget below the minimum: E_INVALID
