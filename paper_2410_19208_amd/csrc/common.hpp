@@ -13,8 +13,16 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 typedef __attribute__((ext_vector_type(2))) double f64x2;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
 enum Prec : int { F64 = 0, F32 = 1, B3 = 2 };
+
+// Global-memory pointers.  Pointers read from the problem descriptor are generic, so accesses
+// through them compile to FLAT instructions, which also count against the LDS wait counter:
+// every wait for an LDS read would then wait for all global loads and stores in flight.
+// Kernels convert descriptor pointers with gp() so that they use global instructions.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ gmem<T>* gp(T* ptr) { return (gmem<T>*)ptr; }
 
 // Tiling constants.  The pass kernels use 16x16 MFMA tiles; a wave owns RB row blocks of 16
 // rows and every column block of the panel.
@@ -162,8 +170,8 @@ __device__ __forceinline__ void upper_tile(int t, int nb, int& I, int& J) {
 }
 
 // Number of eigenvalues of T below x (Sturm sequence).
-__device__ __forceinline__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int r, double x,
-                                           double pivmin) {
+template <typename PD>
+__device__ __forceinline__ int sturm_count(PD d, PD e2, int r, double x, double pivmin) {
   double q = d[0] - x;
   int c = q < 0.0;
   for (int i = 1; i < r; ++i) {

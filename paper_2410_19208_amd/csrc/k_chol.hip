@@ -13,10 +13,12 @@
 // A column whose Schur pivot is below tol * (its Gram diagonal) lies in the span of the
 // previous columns to working precision; it is dropped (zero row of R and zero column of
 // R_JJ^-1, hence a zero column of Q), which leaves the range unchanged.  R goes to H, the
-// inverses of the diagonal blocks to the diagonal blocks of F.
+// inverses of the diagonal blocks to the diagonal blocks of F, both row-major (the apply
+// kernels read 16 consecutive columns per row with 16 lanes).
 //
 // k_apply, rounds 0/1: Q = Y R^-1 by blocked forward substitution on v_mfma_f64_16x16x4f64,
-//   Q_J = (Y_J - sum_{I<J} Q_I R_IJ) R_JJ^-1   (16-column blocks; each wave owns 16 rows).
+//   Q_J = (Y_J - sum_{I<J} Q_I R_IJ) R_JJ^-1   (16-column blocks; each wave owns 16 rows, held
+//   in registers).
 // k_apply, round 2: the rebuild factor W = Q F with F = V_keep diag(sqrt(w)) (row-major out).
 #include "common.hpp"
 #include "launch.hpp"
@@ -35,9 +37,9 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
   const Prob& p = probs[pi];
   const int r = p.r, rp = p.rpad, nb = rp / 16, nt = nb * (nb + 1) / 2;
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, li = lane & 15, kg = lane >> 4;
-  const double* __restrict__ G = p.G;
-  double* __restrict__ H = p.H;
-  double* __restrict__ F = p.F;
+  const gmem<const double>* __restrict__ G = gp((const double*)p.G);
+  gmem<double>* __restrict__ H = gp(p.H);
+  gmem<double>* __restrict__ F = gp(p.F);
   __shared__ double panel[NBMAX][16][17];   // R_JK of the current block row, row-major
   __shared__ double dsm[16][17];            // diagonal tile being factored
   __shared__ double dinv[16][17];           // R_JJ^-1
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int a = 4 * e + kg, c = li;
-        F[(int64_t)(16 * J + c) * rp + 16 * J + a] = dinv[a][c];
+        F[(int64_t)(16 * J + a) * rp + 16 * J + c] = dinv[a][c];   // row-major
       }
     }
     // Per-lane LDS offset (row kg, column li of a 16x17 tile), re-materialised every block so
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int a = 16 * tI[s] + 4 * v + kg, b = 16 * tJ[s] + li;
-      H[(int64_t)b * rp + a] = reg[s][v];
+      H[(int64_t)a * rp + b] = reg[s][v];   // row-major
     }
   }
   lds_barrier();
@@ -196,123 +198,161 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 constexpr int AP_WAVES = 4;
 constexpr int AP_THREADS = AP_WAVES * WAVE;
 
-template <typename T>
-__device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, double* Qs) {
-  const int rp = p.rpad, nb = rp / 16, ld = p.ld, qld = rp + 2;
+// Both rounds keep a wave's 16 rows of Q in registers in the A-operand layout of
+// v_mfma_f64_16x16x4f64: qa[I][kk] of lane (li, kg) is Q[row li][16I + 4kk + kg].  The loops
+// over column blocks are unrolled to NB (the largest block count of the launch), so qa is
+// indexed by constants; blocks past the problem's nb are skipped (J) or contribute exact
+// zeros (I).  A 16x17 LDS scratch per wave turns result-layout blocks into operand layout.
+
+// Result-layout block x (lane: rows 4v + kg, column li) -> operand layout (lane: row li,
+// columns 4kk + kg), through the wave's scratch.
+__device__ __forceinline__ f64x4 to_operand(f64x4 x, double* sc, int li, int kg) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sc[(4 * v + kg) * 17 + li] = x[v];
+  lds_wave_sync();
+  f64x4 out;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) out[kk] = sc[li * 17 + 4 * kk + kg];
+  lds_wave_sync();
+  return out;
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, double* scratch) {
+  const int rp = p.rpad, nb = rp / 16, ld = p.ld;
   const int wave = wave_id(), lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
   const int rowbase = tile * APPLY_ROWS + wave * 16;
-  const T* __restrict__ in = (const T*)((round == 0) ? p.y : p.q1);
-  T* __restrict__ out = (T*)((round == 0) ? p.q1 : p.zm);
-  const double* __restrict__ R = p.H;
-  const double* __restrict__ Dinv = p.F;
-  double* Qw = Qs + (size_t)wave * 16 * qld;   // this wave's 16 rows, row-major
-  for (int J = 0; J < nb; ++J) {
-    f64x4 acc;
+  const gmem<const T>* __restrict__ in = gp((const T*)((round == 0) ? p.y : p.q1));
+  gmem<T>* __restrict__ out = gp((T*)((round == 0) ? p.q1 : p.zm));
+  const gmem<const double>* __restrict__ R = gp((const double*)p.H);
+  const gmem<const double>* __restrict__ Dinv = gp((const double*)p.F);
+  gmem<bf16>* __restrict__ zhi = gp(p.zhi);
+  gmem<bf16>* __restrict__ zlo = gp(p.zlo);
+  double* sc = scratch + wave * 16 * 17;
+  double qa[NB][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = (double)in[(int64_t)(16 * J + li) * ld + rowbase + 4 * v + kg];
-    for (int I = 0; I < J; ++I) {
+  for (int J = 0; J < NB; ++J) {
+    if (J < nb) {   // uniform
+      const gmem<const double>* col = R + (int64_t)kg * rp + 16 * J + li;   // R[kg + 4m][16J + li]
+      f64x4 acc0, acc1 = {0, 0, 0, 0};
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int k = 16 * I + 4 * kk + kg;
-        const double a = Qw[li * qld + k];
-        const double b = R[(int64_t)(16 * J + li) * rp + k];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, b, acc, 0, 0, 0);
+      for (int v = 0; v < 4; ++v) acc0[v] = (double)in[(int64_t)(16 * J + li) * ld + rowbase + 4 * v + kg];
+      double dj[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) dj[kk] = Dinv[(int64_t)(16 * J + 4 * kk + kg) * rp + 16 * J + li];
+      // Y_J - sum_{I<J} Q_I R_IJ, as two chains (even and odd I) added at the end
+#pragma unroll
+      for (int I = 0; I < J; ++I) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double b = col[(int64_t)(16 * I + 4 * kk) * rp];
+          if (I & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-qa[I][kk], b, acc1, 0, 0, 0);
+          else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-qa[I][kk], b, acc0, 0, 0, 0);
+        }
+        if (I & 1) __builtin_amdgcn_sched_barrier(0);   // loads run at most two row blocks ahead
+      }
+      const f64x4 w = to_operand(acc0 + acc1, sc, li, kg);
+      f64x4 q = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) q = __builtin_amdgcn_mfma_f64_16x16x4f64(w[kk], dj[kk], q, 0, 0, 0);
+      const f64x4 qo = to_operand(q, sc, li, kg);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) qa[J][kk] = qo[kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t o = (int64_t)(16 * J + li) * ld + rowbase + 4 * v + kg;
+        const T val = (T)q[v];
+        out[o] = val;
+        if (round == 1 && p.prec == B3) {
+          const bf16 h = (bf16)(float)val;
+          zhi[o] = h;
+          zlo[o] = (bf16)((float)val - (float)h);
+        }
       }
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Qw[(4 * v + kg) * qld + 16 * J + li] = acc[v];
-    lds_wave_sync();   // Qw is this wave's own LDS region
-    f64x4 q = {0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int k = 4 * kk + kg;
-      const double a = Qw[li * qld + 16 * J + k];
-      const double b = Dinv[(int64_t)(16 * J + li) * rp + 16 * J + k];
-      q = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, q, 0, 0, 0);
-    }
-    lds_wave_sync();   // Qw is this wave's own LDS region
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = rowbase + 4 * v + kg;
-      const int64_t o = (int64_t)(16 * J + li) * ld + row;
-      Qw[(4 * v + kg) * qld + 16 * J + li] = q[v];
-      const T val = (T)q[v];
-      out[o] = val;
-      if (round == 1 && p.prec == B3) {
-        const bf16 h = (bf16)(float)val;
-        p.zhi[o] = h;
-        p.zlo[o] = (bf16)((float)val - (float)h);
-      }
-    }
-    lds_wave_sync();   // Qw is this wave's own LDS region
   }
 }
 
 // W = Q F, F = V_keep diag(sqrt(w)) (columns >= r_plus are zero); row-major output.
-template <typename T>
+template <typename T, int NB>
 __device__ __forceinline__ void apply_factor(const Prob& p, int tile) {
   const int rp = p.rpad, nb = rp / 16, ld = p.ld, kw = p.rwpad;
   const int wave = wave_id(), lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
   const int rowbase = tile * APPLY_ROWS + wave * 16;
   const int rplus = min(max(p.iscal[I_RPLUS], 0), rp);
-  const T* __restrict__ Q = (const T*)p.zm;
-  const double* __restrict__ F = p.F;
+  const gmem<const T>* __restrict__ Q = gp((const T*)p.zm);
+  const gmem<const double>* __restrict__ Fm = gp((const double*)p.F);
+  gmem<T>* __restrict__ wf = gp((T*)p.wf);
+  gmem<bf16>* __restrict__ whi = gp(p.whi);
+  gmem<bf16>* __restrict__ wlo = gp(p.wlo);
+  double qa[NB][4];
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int c = min(16 * I + 4 * kk + kg, rp - 1);
+      qa[I][kk] = (I < nb) ? (double)Q[(int64_t)c * ld + rowbase + li] : 0.0;
+    }
   for (int J = 0; J < kw / 16; ++J) {
-    f64x4 acc = {0, 0, 0, 0};
+    f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     if (16 * J < rplus) {
-      const bool colok = (16 * J + li) < rplus;
-      for (int I = 0; I < nb; ++I) {
+      const gmem<const double>* col = Fm + (int64_t)kg * rp + 16 * J + li;   // F[kg + 4m][16J + li]
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-          const int k = 16 * I + 4 * kk + kg;
-          const double a = (double)Q[(int64_t)k * ld + rowbase + li];
-          const double b = colok ? F[(int64_t)(16 * J + li) * rp + k] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          const double b = (I < nb) ? col[(int64_t)min(16 * I + 4 * kk, rp - 4) * rp] : 0.0;
+          if (I & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I][kk], b, acc1, 0, 0, 0);
+          else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I][kk], b, acc0, 0, 0, 0);
         }
+        if (I & 1) __builtin_amdgcn_sched_barrier(0);   // loads run at most two row blocks ahead
       }
     }
+    f64x4 a = acc0 + acc1;
+    // W's columns >= r_plus must be zero (the rebuild reads whole 16/32-column groups); F holds
+    // other data there, and output column li depends on column li of F only
+    if (16 * J + li >= rplus) a = f64x4{0, 0, 0, 0};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t o = (int64_t)(rowbase + 4 * v + kg) * kw + 16 * J + li;
-      if (p.prec == F64) {
-        ((double*)p.wf)[o] = acc[v];
-      } else {
-        const float f = (float)acc[v];
-        ((float*)p.wf)[o] = f;
-        if (p.prec == B3) {
-          const bf16 h = (bf16)f;
-          p.whi[o] = h;
-          p.wlo[o] = (bf16)(f - (float)h);
-        }
+      const T val = (T)a[v];
+      wf[o] = val;
+      if (p.prec == B3) {
+        const bf16 h = (bf16)(float)val;
+        whi[o] = h;
+        wlo[o] = (bf16)((float)val - (float)h);
       }
     }
   }
 }
 
+template <int NB>
 __global__ __launch_bounds__(AP_THREADS) void k_apply(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                       int nprob, int round) {
-  extern __shared__ double qs_smem[];
+  __shared__ double scratch[AP_WAVES * 16 * 17];
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int t = blockIdx.x - tstart[pi];
   if (t * APPLY_ROWS >= p.ld) return;
-  if (round == 2) {
-    if (p.prec == F64) apply_factor<double>(p, t);
-    else apply_factor<float>(p, t);
-  } else {
-    if (p.prec == F64) apply_tri<double>(p, round, t, qs_smem);
-    else apply_tri<float>(p, round, t, qs_smem);
-  }
+  if (p.prec == F64) apply_tri<double, NB>(p, round, t, scratch);
+  else apply_tri<float, NB>(p, round, t, scratch);
+}
+
+template <int NB>
+__global__ __launch_bounds__(AP_THREADS) void k_apply_factor(const Prob* __restrict__ probs,
+                                                             const int* __restrict__ tstart, int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int t = blockIdx.x - tstart[pi];
+  if (t * APPLY_ROWS >= p.ld) return;
+  if (p.prec == F64) apply_factor<double, NB>(p, t);
+  else apply_factor<float, NB>(p, t);
 }
 
 int tiles_small(const Prob&) { return 1; }
 int tiles_apply(const Prob& p) { return p.ld / APPLY_ROWS; }
 
-static size_t apply_smem() { return (size_t)AP_WAVES * 16 * (PSDPROJ_MAX_RANK + 2) * sizeof(double); }
-
-void apply_init() {
-  hipFuncSetAttribute((const void*)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_smem());
-}
+void apply_init() {}
 
 void launch_chol(const Launch& L, int round) {
   if (L.maxnb <= 14)
@@ -321,8 +361,16 @@ void launch_chol(const Launch& L, int round) {
     hipLaunchKernelGGL(k_chol<17>, dim3(L.grid), dim3(CH_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
 }
 void launch_apply(const Launch& L, int round) {
-  hipLaunchKernelGGL(k_apply, dim3(L.grid), dim3(AP_THREADS), apply_smem(), L.stream, L.probs, L.tstart, L.nprob,
-                     round);
+  if (round == 2) {
+    if (L.maxnb <= 14)
+      hipLaunchKernelGGL(k_apply_factor<14>, dim3(L.grid), dim3(AP_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+    else
+      hipLaunchKernelGGL(k_apply_factor<16>, dim3(L.grid), dim3(AP_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
+  } else if (L.maxnb <= 14) {
+    hipLaunchKernelGGL(k_apply<14>, dim3(L.grid), dim3(AP_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
+  } else {
+    hipLaunchKernelGGL(k_apply<16>, dim3(L.grid), dim3(AP_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob, round);
+  }
 }
 
 }  // namespace psd

@@ -9,7 +9,8 @@
 //  k_invit   : eigenvectors of the kept eigenvalues by inverse iteration on T (tridiagonal LU
 //              with partial pivoting), Gram-Schmidt within clusters of close eigenvalues,
 //              back-transformation by the Householder reflectors, and the clamped weights.
-//              Writes V (column c = c-th largest kept eigenvalue) and F = V diag(sqrt(w)).
+//              Writes V (column c = c-th largest kept eigenvalue, column-major) and
+//              F = V diag(sqrt(w)) (row-major).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -26,8 +27,8 @@ __global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, 
   const int lane = threadIdx.x & 63;
   const int r = p.r;
   if (j >= r) return;
-  const double* d = p.td;
-  const double* e2 = p.evals + PSDPROJ_MAX_RANK;
+  const gmem<const double>* d = gp((const double*)p.td);
+  const gmem<const double>* e2 = gp((const double*)p.evals + PSDPROJ_MAX_RANK);
   const double pivmin = p.scal[10];
   double lo = p.scal[8], hi = p.scal[9];
   if (!(isfinite(lo) && isfinite(hi))) {
@@ -98,8 +99,9 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
   __shared__ double U0[PSDPROJ_MAX_RANK], U1[PSDPROJ_MAX_RANK], U2[PSDPROJ_MAX_RANK];
   __shared__ double Lm[PSDPROJ_MAX_RANK], x[PSDPROJ_MAX_RANK], b[PSDPROJ_MAX_RANK];
   __shared__ int piv[PSDPROJ_MAX_RANK];
-  const double* d = p.td;
-  const double* e = p.te;
+  const gmem<const double>* d = gp((const double*)p.td);
+  const gmem<const double>* e = gp((const double*)p.te);
+  gmem<double>* xt = gp(p.xt);
   const double tiny = 2.220446049250313e-16 * fmax(tnorm, 1e-300);
 
   int jc = j0;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
       __syncthreads();
       // --- Gram-Schmidt against earlier members of the cluster (stored in xt)
       for (int m = j0; m < jc; ++m) {
-        const double* xm = p.xt + (int64_t)(m - nu) * rp;
+        const gmem<double>* xm = xt + (int64_t)(m - nu) * rp;
         double s = 0.0;
         for (int i = lane; i < r; i += WAVE) s += xm[i] * x[i];
         s = wave_sum(s);
@@ -164,13 +166,13 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
       __syncthreads();
     }
     // b holds the unit eigenvector of T; keep it for later cluster members
-    double* xs = p.xt + (int64_t)(jc - nu) * rp;
+    gmem<double>* xs = xt + (int64_t)(jc - nu) * rp;
     for (int i = lane; i < r; i += WAVE) xs[i] = b[i];
     // --- back-transform u = H_0 H_1 ... H_{r-3} b
     for (int jh = r - 3; jh >= 0; --jh) {
       const double tau = p.tau[jh];
       if (tau == 0.0) continue;
-      const double* col = p.H + (int64_t)jh * rp;
+      const gmem<const double>* col = gp((const double*)p.H) + (int64_t)jh * rp;
       double s = 0.0;
       for (int i = jh + 1 + lane; i < r; i += WAVE) s += ((i == jh + 1) ? 1.0 : col[i]) * b[i];
       s = wave_sum(s) * tau;
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
     for (int i = lane; i < rp; i += WAVE) {
       const double u = (i < r) ? b[i] : 0.0;
       p.V[(int64_t)c * rp + i] = u;
-      p.F[(int64_t)c * rp + i] = u * sw;
+      p.F[(int64_t)i * rp + c] = u * sw;   // row-major (read by the factor apply)
     }
     __syncthreads();
     ++jc;

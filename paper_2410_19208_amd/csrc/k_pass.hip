@@ -47,7 +47,8 @@ __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict
   const int kend = min(n, kbeg + p.kchunk);
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int lrow = lane & 15, kg = lane >> 4;
-  const double* __restrict__ A = (const double*)p.A;
+  const gmem<const double>* __restrict__ A = gp((const double*)p.A);
+  const gmem<const double>* __restrict__ Zm = gp((const double*)p.zm);
   const int64_t lda = p.lda;
 
   f64x4 acc[NCB];
@@ -62,10 +63,10 @@ __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict
     double a[KPL];
     const int c0 = kk + kg * KPL;
     if (rows_full && kk + BK <= n) {
-      const double* src = A + (int64_t)rowg * lda + c0;
+      const gmem<const double>* src = A + (int64_t)rowg * lda + c0;
 #pragma unroll
       for (int v = 0; v < KPL; v += 2) {
-        f64x2 x = __builtin_nontemporal_load((const f64x2*)(src + v));
+        f64x2 x = __builtin_nontemporal_load((const gmem<f64x2>*)(src + v));
         a[v] = x[0]; a[v + 1] = x[1];
       }
     } else {
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict
     // ---- Z slice [kk, kk+BK) x [0, NC) into LDS (column-major, padded)
     for (int c = threadIdx.x; c < NC * CH; c += PASS_THREADS) {
       const int col = c / CH, ch = c - col * CH;
-      const unsigned char* src = (const unsigned char*)((const double*)p.zm + (int64_t)col * ld + kk) + ch * 16;
-      *(uint4*)(lds + col * CSTRIDE + ch * 16) = *(const uint4*)src;
+      const gmem<const u32x4>* src = (const gmem<const u32x4>*)(Zm + (int64_t)col * ld + kk) + ch;
+      *(u32x4*)(lds + col * CSTRIDE + ch * 16) = *src;
     }
     __syncthreads();
 #pragma unroll
@@ -163,7 +164,7 @@ __device__ __forceinline__ void pl_issue(const PlArgs& g, unsigned char* stage, 
       const int c = (lane & 7) ^ ((i & 15) >> 1);
       const int row = min(m0 + i, n - 1);
       const int col = k0 + 4 * c;
-      const float* src = g.A + (int64_t)row * g.lda;
+      const gmem<const float>* src = gp(g.A) + (int64_t)row * g.lda;
       f32x4 v;
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = (col + e < n) ? src[col + e] : 0.0f;

@@ -66,13 +66,13 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __rest
   const int n = p.n, ld = p.ld;
   const int nb = (n + GEMV_TILE - 1) / GEMV_TILE;
   const int pp = p.iscal[I_PP] & 1;
-  const double* __restrict__ vin = p.vec + (int64_t)pp * ld;
-  double* __restrict__ vout = p.vec + (int64_t)(1 - pp) * ld;
+  const gmem<const double>* __restrict__ vin = gp((const double*)p.vec) + (int64_t)pp * ld;
+  gmem<double>* __restrict__ vout = gp(p.vec) + (int64_t)(1 - pp) * ld;
   const double inv = p.scal[S_INV];
   const double shift = p.scal[S_SHIFT];
   const int x = threadIdx.x;
   const int row = b * GEMV_TILE + x;
-  const double* __restrict__ part = p.gvp + (int64_t)b * nb * GEMV_TILE;
+  const gmem<const double>* __restrict__ part = gp((const double*)p.gvp) + (int64_t)b * nb * GEMV_TILE;
   double y = 0.0;
   if (row < n) {
     double s = 0.0;
@@ -116,9 +116,9 @@ __device__ void gemv_tile(const Prob& p, int t) {
   gemv_tile_ij(t, I, J);
   const bool diag = (I == J);
   const int pp = p.iscal[I_PP] & 1;                 // ping-pong: read vec[pp], write vec[1-pp]
-  const double* __restrict__ vin = p.vec + (int64_t)pp * ld;
+  const gmem<const double>* __restrict__ vin = gp((const double*)p.vec) + (int64_t)pp * ld;
   const double inv = p.scal[S_INV];
-  const T* __restrict__ A = (const T*)p.A;
+  const gmem<const T>* __restrict__ A = gp((const T*)p.A);
   const int64_t lda = p.lda;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   __shared__ double cred[GEMV_THREADS / WAVE][GEMV_TILE];
@@ -131,21 +131,21 @@ __device__ void gemv_tile(const Prob& p, int t) {
   // full tile columns and 16-byte aligned rows: vector loads; otherwise masked element loads
   const bool vec = p.avec && (J * GEMV_TILE + GEMV_TILE <= n);
   double yc[4] = {0.0, 0.0, 0.0, 0.0};
-  double* __restrict__ gvp = p.gvp;
+  gmem<double>* __restrict__ gvp = gp(p.gvp);
 
   // batch loads: rows r0 .. r0+RB-1 (clamped to n-1; rows past n are zeroed when used)
   auto load = [&](T (&a)[RB][4], int r0) {
     if (vec) {
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
-        const T* src = A + (int64_t)min(r0 + q, n - 1) * lda + c0;
+        const gmem<const T>* src = A + (int64_t)min(r0 + q, n - 1) * lda + c0;
         if constexpr (sizeof(T) == 4) {
-          const f32x4 x = __builtin_nontemporal_load((const f32x4*)src);
+          const f32x4 x = __builtin_nontemporal_load((const gmem<f32x4>*)src);
 #pragma unroll
           for (int e = 0; e < 4; ++e) a[q][e] = x[e];
         } else {
-          const f64x2 x0 = __builtin_nontemporal_load((const f64x2*)src);
-          const f64x2 x1 = __builtin_nontemporal_load((const f64x2*)(src + 2));
+          const f64x2 x0 = __builtin_nontemporal_load((const gmem<f64x2>*)src);
+          const f64x2 x1 = __builtin_nontemporal_load((const gmem<f64x2>*)(src + 2));
           a[q][0] = x0[0]; a[q][1] = x0[1]; a[q][2] = x1[0]; a[q][3] = x1[1];
         }
       }

@@ -45,6 +45,8 @@ __device__ void rebuild_tile(const Prob& p, int t) {
   const int l16 = lane & 15, kg = lane >> 4;
   const int rplus = min(max(p.iscal[I_RPLUS], 0), p.rpad);
   const int kw = p.rwpad;
+  const gmem<const bf16>* __restrict__ whi = gp((const bf16*)p.whi);
+  const gmem<const bf16>* __restrict__ wlo = gp((const bf16*)p.wlo);
   Acc acc[2][8];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -58,15 +60,15 @@ __device__ void rebuild_tile(const Prob& p, int t) {
     if constexpr (PREC == B3) {
       const int kk = k0 + kg * 8;
       bf16x8 ahi[2], alo[2];
-      ahi[0] = *(const bf16x8*)(p.whi + (int64_t)ra0 * kw + kk);
-      alo[0] = *(const bf16x8*)(p.wlo + (int64_t)ra0 * kw + kk);
-      ahi[1] = *(const bf16x8*)(p.whi + (int64_t)ra1 * kw + kk);
-      alo[1] = *(const bf16x8*)(p.wlo + (int64_t)ra1 * kw + kk);
+      ahi[0] = *(const gmem<bf16x8>*)(whi + (int64_t)ra0 * kw + kk);
+      alo[0] = *(const gmem<bf16x8>*)(wlo + (int64_t)ra0 * kw + kk);
+      ahi[1] = *(const gmem<bf16x8>*)(whi + (int64_t)ra1 * kw + kk);
+      alo[1] = *(const gmem<bf16x8>*)(wlo + (int64_t)ra1 * kw + kk);
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) {
         const int rbw = J0 + cb * 16 + l16;
-        const bf16x8 bhi = *(const bf16x8*)(p.whi + (int64_t)rbw * kw + kk);
-        const bf16x8 blo = *(const bf16x8*)(p.wlo + (int64_t)rbw * kw + kk);
+        const bf16x8 bhi = *(const gmem<bf16x8>*)(whi + (int64_t)rbw * kw + kk);
+        const bf16x8 blo = *(const gmem<bf16x8>*)(wlo + (int64_t)rbw * kw + kk);
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           acc[a][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], bhi, acc[a][cb], 0, 0, 0);
@@ -75,24 +77,24 @@ __device__ void rebuild_tile(const Prob& p, int t) {
         }
       }
     } else if constexpr (PREC == F32) {
-      const float* W = (const float*)p.wf;
+      const gmem<const float>* W = gp((const float*)p.wf);
       const int kk = k0 + kg * 4;
-      const float4 a0 = *(const float4*)(W + (int64_t)ra0 * kw + kk);
-      const float4 a1 = *(const float4*)(W + (int64_t)ra1 * kw + kk);
+      const f32x4 a0 = *(const gmem<f32x4>*)(W + (int64_t)ra0 * kw + kk);
+      const f32x4 a1 = *(const gmem<f32x4>*)(W + (int64_t)ra1 * kw + kk);
 #pragma unroll
       for (int cb = 0; cb < 8; ++cb) {
-        const float4 b = *(const float4*)(W + (int64_t)(J0 + cb * 16 + l16) * kw + kk);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b.x, acc[0][cb], 0, 0, 0);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b.y, acc[0][cb], 0, 0, 0);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, b.z, acc[0][cb], 0, 0, 0);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, b.w, acc[0][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b.x, acc[1][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b.y, acc[1][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, b.z, acc[1][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, b.w, acc[1][cb], 0, 0, 0);
+        const f32x4 b = *(const gmem<f32x4>*)(W + (int64_t)(J0 + cb * 16 + l16) * kw + kk);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[0], b[0], acc[0][cb], 0, 0, 0);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[1], b[1], acc[0][cb], 0, 0, 0);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[2], b[2], acc[0][cb], 0, 0, 0);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[3], b[3], acc[0][cb], 0, 0, 0);
+        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[0], b[0], acc[1][cb], 0, 0, 0);
+        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[1], b[1], acc[1][cb], 0, 0, 0);
+        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2], b[2], acc[1][cb], 0, 0, 0);
+        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b[3], acc[1][cb], 0, 0, 0);
       }
     } else {
-      const double* W = (const double*)p.wf;
+      const gmem<const double>* W = gp((const double*)p.wf);
       const int kk = k0 + kg;
       const double a0 = W[(int64_t)ra0 * kw + kk];
       const double a1 = W[(int64_t)ra1 * kw + kk];
@@ -113,7 +115,7 @@ __device__ void rebuild_tile(const Prob& p, int t) {
       for (int v = 0; v < 4; ++v)
         tile[(wave * 32 + a * 16 + acc_row<PREC == F64>(kg, v)) * LDT + cb * 16 + l16] = (T)acc[a][cb][v];
   __syncthreads();
-  T* P = (T*)p.P;
+  gmem<T>* P = gp((T*)p.P);
   const int64_t ldp = p.ldp;
   if (I == J) {
     for (int e = threadIdx.x; e < TS * TS; e += RB_THREADS) {

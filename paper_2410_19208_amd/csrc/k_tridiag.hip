@@ -55,6 +55,11 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int r = p.r, rp = p.rpad, nb = rp / 16;
+  const gmem<const double>* __restrict__ Cm = gp((const double*)p.C);
+  gmem<double>* __restrict__ Hm = gp(p.H);
+  gmem<double>* __restrict__ tdm = gp(p.td);
+  gmem<double>* __restrict__ tem = gp(p.te);
+  gmem<double>* __restrict__ taum = gp(p.tau);
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, lr = lane >> 2, lc = lane & 3;
   __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];
   __shared__ double rpart[TD_NB][TD_NB][16];   // [I][J][row]: C_IJ v_J
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int a = 16 * I + lr, b = 16 * J + 4 * lc + q;
-      reg[s][q] = ok ? p.C[(int64_t)b * rp + a] : 0.0;
+      reg[s][q] = ok ? Cm[(int64_t)b * rp + a] : 0.0;
     }
   }
 
@@ -113,11 +118,11 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
       sc = 1.0 / (alpha - beta);
     }
     if (tid == 0) {
-      p.td[j] = buf[j];
-      p.te[j] = beta;
-      p.tau[j] = tau;
+      tdm[j] = buf[j];
+      tem[j] = beta;
+      taum[j] = tau;
     }
-    for (int i = j + 2 + tid; i < r; i += TD_THREADS) p.H[(int64_t)j * rp + i] = buf[i] * sc;
+    for (int i = j + 2 + tid; i < r; i += TD_THREADS) Hm[(int64_t)j * rp + i] = buf[i] * sc;
     if (tau == 0.0) continue;   // uniform: every wave computed the same tau
     // v_i: 0 (i <= j), 1 (i = j+1), buf[i] * sc (i >= j+2); padding (>= r) is zero in buf
     auto vval = [&](int i, double x) { return (i > j + 1) ? x * sc : (i == j + 1 ? 1.0 : 0.0); };
