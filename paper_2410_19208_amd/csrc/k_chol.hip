@@ -287,25 +287,55 @@ __device__ __forceinline__ void apply_factor(const Prob& p, int tile) {
   gmem<bf16>* __restrict__ wlo = gp(p.wlo);
   double qa[NB][4];
 #pragma unroll
-  for (int I = 0; I < NB; ++I)
+  for (int I = 0; I < NB; ++I) {
+    if (I < nb) {   // uniform
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int c = min(16 * I + 4 * kk + kg, rp - 1);
-      qa[I][kk] = (I < nb) ? (double)Q[(int64_t)c * ld + rowbase + li] : 0.0;
+      for (int kk = 0; kk < 4; ++kk) qa[I][kk] = (double)Q[(int64_t)(16 * I + 4 * kk + kg) * ld + rowbase + li];
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) qa[I][kk] = 0.0;
     }
+  }
+#pragma unroll 1
   for (int J = 0; J < kw / 16; ++J) {
     f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     if (16 * J < rplus) {
       const gmem<const double>* col = Fm + (int64_t)kg * rp + 16 * J + li;   // F[kg + 4m][16J + li]
+      // opaque to loop-invariant code motion, which would otherwise precompute all 4*NB load
+      // addresses outside the J loop (2*4*NB registers)
+      __asm__ volatile("" : "+v"(col));
+      auto load = [&](double (&b)[4], int I) {
 #pragma unroll
-      for (int I = 0; I < NB; ++I) {
+        for (int kk = 0; kk < 4; ++kk) b[kk] = col[(int64_t)(16 * I + 4 * kk) * rp];
+      };
+      auto mfma4 = [&](const double (&b)[4], int I) {   // one chain per parity of I
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-          const double b = (I < nb) ? col[(int64_t)min(16 * I + 4 * kk, rp - 4) * rp] : 0.0;
-          if (I & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I][kk], b, acc1, 0, 0, 0);
-          else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I][kk], b, acc0, 0, 0, 0);
+          if (I & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I][kk], b[kk], acc1, 0, 0, 0);
+          else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[I][kk], b[kk], acc0, 0, 0, 0);
         }
-        if (I & 1) __builtin_amdgcn_sched_barrier(0);   // loads run at most two row blocks ahead
+      };
+      if (nb == NB) {
+        // loads run two row blocks ahead of the MFMAs (a ring of three register blocks); the
+        // scheduling barrier keeps each prefetch ahead of the MFMAs that follow it
+        double ring[3][4];
+        load(ring[0], 0);
+        load(ring[1], 1);
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+          if (I + 2 < NB) load(ring[(I + 2) % 3], I + 2);
+          __builtin_amdgcn_sched_barrier(0);
+          mfma4(ring[I % 3], I);
+        }
+      } else {
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+          if (I < nb) {   // uniform
+            double b[4];
+            load(b, I);
+            mfma4(b, I);
+          }
+        }
       }
     }
     f64x4 a = acc0 + acc1;
