@@ -107,6 +107,14 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// 16 bytes per lane from global memory into LDS at dst + 16 * lane (dst wave-uniform), without
+// a VGPR round trip (global_load_lds_dwordx4); complete after this wave's vmcnt reaches 0.
+__device__ __forceinline__ void dma16(const void* g, unsigned char* dst) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void*)dst, 16, 0, 0);
+}
+
 // Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits for every
 // outstanding global load and store of the wave (a round trip to L2 after a store); loops whose
 // waves exchange data through LDS alone use this one.

@@ -116,13 +116,6 @@ constexpr int PL_ABYTES = PL_BM * PL_BK * 4;     // A slice: 32 blocks of 1 KB (
 // LDS bytes of one step: A slice + Z slice (2 KB per 16 columns: hi and lo, or FP32).
 __host__ __device__ constexpr int pl_stage_bytes(int ncb) { return PL_ABYTES + ncb * 2048; }
 
-typedef __attribute__((address_space(3))) void lds_void;
-
-// 16 bytes per lane from global memory into LDS at dst + 16 * lane (dst wave-uniform).
-__device__ __forceinline__ void dma16(const void* g, unsigned char* dst) {
-  __builtin_amdgcn_global_load_lds(g, (lds_void*)dst, 16, 0, 0);
-}
-
 // Operand pointers and sizes of one pass, held in registers (the descriptor is read once).
 struct PlArgs {
   const float* A; int64_t lda;

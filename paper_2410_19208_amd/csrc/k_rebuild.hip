@@ -34,7 +34,7 @@ __device__ void rebuild_tile(const Prob& p, int t) {
   typedef typename RbCfg<PREC>::Acc Acc;
   constexpr int TS = RB_TILE;                       // 128
   constexpr int LDT = TS + 1;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  extern __shared__ __attribute__((aligned(1024))) unsigned char smem[];
   T* tile = (T*)smem;                               // [TS][LDT]
 
   int I, J;
@@ -56,45 +56,9 @@ __device__ void rebuild_tile(const Prob& p, int t) {
   const int ra0 = I0 + wave * 32 + l16;
   const int ra1 = ra0 + 16;
   constexpr int KS = RbCfg<PREC>::KS;
-  for (int k0 = 0; k0 < rplus; k0 += KS) {
-    if constexpr (PREC == B3) {
-      const int kk = k0 + kg * 8;
-      bf16x8 ahi[2], alo[2];
-      ahi[0] = *(const gmem<bf16x8>*)(whi + (int64_t)ra0 * kw + kk);
-      alo[0] = *(const gmem<bf16x8>*)(wlo + (int64_t)ra0 * kw + kk);
-      ahi[1] = *(const gmem<bf16x8>*)(whi + (int64_t)ra1 * kw + kk);
-      alo[1] = *(const gmem<bf16x8>*)(wlo + (int64_t)ra1 * kw + kk);
-#pragma unroll
-      for (int cb = 0; cb < 8; ++cb) {
-        const int rbw = J0 + cb * 16 + l16;
-        const bf16x8 bhi = *(const gmem<bf16x8>*)(whi + (int64_t)rbw * kw + kk);
-        const bf16x8 blo = *(const gmem<bf16x8>*)(wlo + (int64_t)rbw * kw + kk);
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          acc[a][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], bhi, acc[a][cb], 0, 0, 0);
-          acc[a][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[a], blo, acc[a][cb], 0, 0, 0);
-          acc[a][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[a], bhi, acc[a][cb], 0, 0, 0);
-        }
-      }
-    } else if constexpr (PREC == F32) {
-      const gmem<const float>* W = gp((const float*)p.wf);
-      const int kk = k0 + kg * 4;
-      const f32x4 a0 = *(const gmem<f32x4>*)(W + (int64_t)ra0 * kw + kk);
-      const f32x4 a1 = *(const gmem<f32x4>*)(W + (int64_t)ra1 * kw + kk);
-#pragma unroll
-      for (int cb = 0; cb < 8; ++cb) {
-        const f32x4 b = *(const gmem<f32x4>*)(W + (int64_t)(J0 + cb * 16 + l16) * kw + kk);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[0], b[0], acc[0][cb], 0, 0, 0);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[1], b[1], acc[0][cb], 0, 0, 0);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[2], b[2], acc[0][cb], 0, 0, 0);
-        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[3], b[3], acc[0][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[0], b[0], acc[1][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[1], b[1], acc[1][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2], b[2], acc[1][cb], 0, 0, 0);
-        acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b[3], acc[1][cb], 0, 0, 0);
-      }
-    } else {
-      const gmem<const double>* W = gp((const double*)p.wf);
+  if constexpr (PREC == F64) {
+    const gmem<const double>* W = gp((const double*)p.wf);
+    for (int k0 = 0; k0 < rplus; k0 += KS) {
       const int kk = k0 + kg;
       const double a0 = W[(int64_t)ra0 * kw + kk];
       const double a1 = W[(int64_t)ra1 * kw + kk];
@@ -105,6 +69,84 @@ __device__ void rebuild_tile(const Prob& p, int t) {
         acc[1][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][cb], 0, 0, 0);
       }
     }
+  } else {
+    // The K-slice of W_J (rows J0 .. J0+127, 64 bytes of K each: 32 bf16 or 16 floats) is
+    // shared by the four waves: it goes global -> LDS by direct loads into a two-slice ring
+    // (block cb holds rows 16cb .. 16cb+15 at 64 bytes each, 16-byte slot s of row j holding
+    // chunk s ^ ((j % 16) / 4), so each 16-lane read hits 16 distinct bank groups; BF16X3
+    // keeps hi in blocks 0..7 and lo in 8..15).  Each wave's own rows of W_I are prefetched
+    // into registers one slice ahead.  The staging tile below reuses the same LDS.
+    constexpr int NBLK = (PREC == B3) ? 16 : 8;
+    constexpr int SLICE = NBLK * 1024;
+    const int nks = (rplus + KS - 1) / KS;
+    const gmem<const float>* Wf = gp((const float*)p.wf);
+    auto issue = [&](int ks) {
+      unsigned char* dst = smem + (ks & 1) * SLICE;
+      const int k0 = ks * KS;
+      const int j = lane >> 2, c = (lane & 3) ^ (j >> 2);
+#pragma unroll
+      for (int u = 0; u < NBLK / 4; ++u) {
+        const int b = wave + 4 * u;
+        const int cb = b & 7;
+        const int64_t row = J0 + cb * 16 + j;
+        if constexpr (PREC == B3) dma16((const void*)(((b < 8) ? whi : wlo) + row * kw + k0 + 8 * c), dst + b * 1024);
+        else dma16((const void*)(Wf + row * kw + k0 + 4 * c), dst + b * 1024);
+      }
+    };
+    typedef typename std::conditional<PREC == B3, bf16x8, f32x4>::type Frag;
+    Frag an[4];   // B3: hi rows ra0, ra1 then lo rows ra0, ra1; F32: rows ra0, ra1
+    auto load_a = [&](int ks) {
+      const int k0 = ks * KS;
+      if constexpr (PREC == B3) {
+        const int kk = k0 + kg * 8;
+        an[0] = *(const gmem<bf16x8>*)(whi + (int64_t)ra0 * kw + kk);
+        an[1] = *(const gmem<bf16x8>*)(whi + (int64_t)ra1 * kw + kk);
+        an[2] = *(const gmem<bf16x8>*)(wlo + (int64_t)ra0 * kw + kk);
+        an[3] = *(const gmem<bf16x8>*)(wlo + (int64_t)ra1 * kw + kk);
+      } else {
+        const int kk = k0 + kg * 4;
+        an[0] = *(const gmem<f32x4>*)(Wf + (int64_t)ra0 * kw + kk);
+        an[1] = *(const gmem<f32x4>*)(Wf + (int64_t)ra1 * kw + kk);
+      }
+    };
+    if (nks > 0) {
+      issue(0);
+      load_a(0);
+    }
+    const int boff = l16 * 64 + ((kg ^ (l16 >> 2)) << 4);
+    for (int ks = 0; ks < nks; ++ks) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's slice loads and A rows
+      lds_barrier();                        // everyone's slice; reads of the other slice done
+      Frag a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = an[q];
+      if (ks + 1 < nks) {
+        issue(ks + 1);
+        load_a(ks + 1);
+      }
+      const unsigned char* sl = smem + (ks & 1) * SLICE;
+#pragma unroll
+      for (int cb = 0; cb < 8; ++cb) {
+        if constexpr (PREC == B3) {
+          const bf16x8 bhi = *(const bf16x8*)(sl + cb * 1024 + boff);
+          const bf16x8 blo = *(const bf16x8*)(sl + (8 + cb) * 1024 + boff);
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bhi, acc[r][cb], 0, 0, 0);
+            acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], blo, acc[r][cb], 0, 0, 0);
+            acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2 + r], bhi, acc[r][cb], 0, 0, 0);
+          }
+        } else {
+          const f32x4 b = *(const f32x4*)(sl + cb * 1024 + boff);
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              acc[r][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][e], b[e], acc[r][cb], 0, 0, 0);
+        }
+      }
+    }
+    lds_barrier();   // the staging tile overwrites the ring
   }
   // stage: lane holds rows acc_row(kg, v) of 16-row block a, column cb*16 + l16
 #pragma unroll
