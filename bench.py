@@ -6,7 +6,9 @@ SuiteSparse matrices): n = 20000, A = U diag(lam) U^T stored in FP32 (1.6 GB), U
 5% of lam decaying exponentially from 10 to 1e-4 and the rest uniform in [-1, 0];
 k = 200, p = 20, q = 1.  One step = one plain projection (Alg. 2) and one scaled
 projection (Alg. 3 with alpha estimated by Alg. 5, N = 10) of the same resident matrix,
-both through the C ABI (psdproj_run) with the split-BF16 (bf16x3) MFMA passes.
+run as one grouped launch sequence through the C ABI (psdproj_batch) with the split-BF16
+(bf16x3) MFMA passes; the same two projections one after the other (psdproj_run each) are
+timed beside it.
 
 Prints one JSON line (see the repository's design notes for the field definitions).
 """
@@ -47,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (parity and CPU timing)")
     ap.add_argument("--no-fp32-compare", action="store_true", help="skip timing the plain FP32 form")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sequential", action="store_true",
+                    help="time the step as two psdproj_run calls instead of one grouped psdproj_batch")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve"],
                     help="step: the headline n=20000 step (default); batch: 256 uneven problems in one "
                          "grouped launch sequence; serve: Poisson arrivals through the request server")
@@ -68,7 +72,7 @@ def main() -> int:
 
     import paper_2410_19208_amd as pp
     import workloads
-    from paper_2410_19208_amd.torch_api import Projector
+    from paper_2410_19208_amd.torch_api import BatchProjector, Projector
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -97,17 +101,24 @@ def main() -> int:
     plain = Projector(n, k, p, q, "plain", args.precision, seed=args.seed, device=dev)
     scaled = Projector(n, k, p, q, "scaled", args.precision, seed=args.seed, alpha=0.0,
                        alpha_iters=args.alpha_iters, device=dev)
+    both = BatchProjector([dict(n=n, k=k, p=p, q=q, variant="plain", precision=args.precision, seed=args.seed),
+                           dict(n=n, k=k, p=p, q=q, variant="scaled", precision=args.precision, seed=args.seed,
+                                alpha=0.0, alpha_iters=args.alpha_iters)], device=dev)
     P1 = torch.empty_like(A)
     P2 = torch.empty_like(A)
 
-    def step():
+    def step_sequential():
         plain(A, P1)
         scaled(A, P2)
 
+    def step_grouped():
+        both([A, A], [P1, P2])
+
+    step = step_sequential if args.sequential else step_grouped
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    r1, r2 = plain.result(), scaled.result()
+    r1, r2 = (plain.result(), scaled.result()) if args.sequential else tuple(both.results())
     if r1.status or r2.status:
         log(f"device status plain={r1.status} scaled={r2.status}")
         return 1
@@ -142,7 +153,15 @@ def main() -> int:
 
     ms_plain = one(plain, P1)
     ms_scaled = one(scaled, P2)
-    r1, r2 = plain.result(), scaled.result()
+    other = step_grouped if args.sequential else step_sequential
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        other()
+    torch.cuda.synchronize()
+    ms_other = 1e3 * (time.perf_counter() - t) / 3
+    step()
+    torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- algorithmic work
     es = 8 if args.precision == "fp64" else 4
@@ -156,25 +175,33 @@ def main() -> int:
     tflops = (flops_plain + flops_scaled) / step_s / 1e12
     gbs = (bytes_plain + bytes_scaled) / step_s / 1e9
 
-    # roofline of the dominant kernel (largest device time in the timed region)
+    # roofline of the dominant kernel (largest device time in the timed region).  A grouped
+    # launch covers every problem active in its stage, so the algorithmic bytes of one launch
+    # are the per-problem figure times the problem-launches of the step over its launches.
     dom = max(kern, key=lambda kname: kern[kname]["total_ms"])
     d = kern[dom]
     bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
+    launches_per_step = d["launches"] / args.steps
     if dom == "k_gemv":
-        alg = n * (n + 1) / 2 * es + 2 * n * 8.0
+        per_unit = n * (n + 1) / 2 * es + 2 * n * 8.0
+        units = 2 * (args.alpha_iters + 1)
         note = "upper triangle of the symmetric A read once per product plus two FP64 vectors"
     elif dom == "k_pass":
-        alg = nn * es  # A streamed once per pass (the Z panel is L2/MALL resident)
-        note = "A read once per pass"
+        per_unit = nn * es  # A streamed once per pass (the Z panel is L2/MALL resident)
+        units = 2 * passes
+        note = "A read once per pass and problem"
     elif dom == "k_rebuild":
-        alg = nn * es
-        note = "P written once"
+        per_unit = nn * es
+        units = 2
+        note = "P written once per problem"
     else:
-        alg = float("nan")
+        per_unit, units = float("nan"), 1
         note = "no algorithmic byte model for this kernel"
+    alg = per_unit * units / launches_per_step
     achieved = alg / (d["avg_us"] * 1e-6) / 1e9
     roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": None, "algorithmic_bytes_per_launch": alg,
+                "problems_per_launch": round(units / launches_per_step, 3),
                 "avg_launch_us": round(d["avg_us"], 2), "model": note}
 
     out = {
@@ -183,7 +210,9 @@ def main() -> int:
         "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
         "config": {"workload": f"large_20k: n={n}, k={k}, p={p}, q={q}; one plain (Alg. 2) + one scaled (Alg. 3, "
                                f"alpha by Alg. 5 with N={args.alpha_iters}) projection per step; A fp32 resident",
-                   "n": n, "k": k, "p": p, "q": q, "precision": args.precision},
+                   "n": n, "k": k, "p": p, "q": q, "precision": args.precision,
+                   "step": "two psdproj_run calls" if args.sequential else "one grouped psdproj_batch of both"},
+        "ms_per_step_" + ("grouped" if args.sequential else "sequential"): round(ms_other, 4),
         "tflops": round(tflops, 2), "hbm_gbs": round(gbs, 1),
         "latency_ms": {"plain": round(ms_plain, 3), "scaled": round(ms_scaled, 3)},
         "r_plus": {"plain": r1.r_plus, "scaled": r2.r_plus}, "alpha": r2.alpha_used,
