@@ -106,10 +106,73 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __rest
   }
 }
 
-// RB rows per load batch: 16 for FP32 storage, 8 for FP64 (64 VGPRs of A in flight per lane).
-template <typename T, int RB>
-__device__ void gemv_tile(const Prob& p, int t) {
+// Stream one wave's 64 rows of a tile in batches of RB rows, double-buffered in registers (the
+// loop is fully unrolled, so the loads of batch bt+1 are in flight while batch bt is used and
+// no copy between the buffers forces an early wait).  VEC: full tile columns and 16-byte
+// aligned rows, one 16-byte load per row and lane; otherwise element loads at clamped
+// addresses with the values past column n zeroed.  Rows past n are loaded clamped to row
+// n-1; their row sums land in partial slots that are never read and their column terms are
+// multiplied by a zero v_I.
+template <typename T, int RB, bool VEC>
+__device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A, int64_t lda, int n, int rw, int c0,
+                                            const double (&vj)[4], double vrow, double (&yc)[4],
+                                            gmem<double>* __restrict__ rowout, int lane) {
+  constexpr int NBT = 64 / RB;
   constexpr int LOGRB = (RB == 16) ? 4 : 3;
+  T a[2][RB][4];
+  auto load = [&](T (&dst)[RB][4], int r0) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int64_t row = (int64_t)min(r0 + q, n - 1) * lda;
+      if constexpr (VEC) {
+        if constexpr (sizeof(T) == 4) {
+          const f32x4 x = __builtin_nontemporal_load((const gmem<f32x4>*)(A + row + c0));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dst[q][e] = x[e];
+        } else {
+          const f64x2 x0 = __builtin_nontemporal_load((const gmem<f64x2>*)(A + row + c0));
+          const f64x2 x1 = __builtin_nontemporal_load((const gmem<f64x2>*)(A + row + c0 + 2));
+          dst[q][0] = x0[0]; dst[q][1] = x0[1]; dst[q][2] = x1[0]; dst[q][3] = x1[1];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const T x = A[row + min(c0 + e, n - 1)];
+          dst[q][e] = (c0 + e < n) ? x : (T)0;
+        }
+      }
+    }
+  };
+  load(a[0], rw);
+#pragma unroll
+  for (int bt = 0; bt < NBT; ++bt) {
+    // keep the scheduler from hoisting later batches' loads (they would need more buffers)
+    __builtin_amdgcn_sched_barrier(0);
+    if (bt + 1 < NBT) load(a[(bt + 1) & 1], rw + (bt + 1) * RB);
+    double rs[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      double x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = (double)a[bt & 1][q][e];
+      rs[q] = x[0] * vj[0] + x[1] * vj[1] + x[2] * vj[2] + x[3] * vj[3];
+      const double vi = bcast_f64(vrow, bt * RB + q);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        yc[e] += x[e] * vi;
+        // pin the column update to its row: otherwise it is deferred past the row sums and
+        // every converted row stays live
+        __asm__ volatile("" : "+v"(yc[e]));
+      }
+    }
+    reduce_scatter<RB>(rs, lane);
+    if ((lane & ((64 / RB) - 1)) == 0) rowout[bt * RB + (lane >> (6 - LOGRB))] = rs[0];
+  }
+}
+
+// RB rows per load batch: 16 for FP32 storage, 8 for FP64 (64 VGPRs of A per buffer).
+template <typename T, int RB>
+__device__ __forceinline__ void gemv_tile(const Prob& p, int t) {
   const int n = p.n, ld = p.ld;
   const int nb = (n + GEMV_TILE - 1) / GEMV_TILE;
   int I, J;
@@ -118,83 +181,34 @@ __device__ void gemv_tile(const Prob& p, int t) {
   const int pp = p.iscal[I_PP] & 1;                 // ping-pong: read vec[pp], write vec[1-pp]
   const gmem<const double>* __restrict__ vin = gp((const double*)p.vec) + (int64_t)pp * ld;
   const double inv = p.scal[S_INV];
-  const gmem<const T>* __restrict__ A = gp((const T*)p.A);
-  const int64_t lda = p.lda;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   __shared__ double cred[GEMV_THREADS / WAVE][GEMV_TILE];
 
-  // lane owns columns c0 .. c0+3 of the tile, the wave rows I*256 + wave*64 + [0, 64)
+  // lane owns columns c0 .. c0+3 of the tile, the wave rows rw .. rw+63
   const int c0 = J * GEMV_TILE + 4 * lane;
+  const int rw = I * GEMV_TILE + wave * 64;
   double vj[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) vj[e] = (c0 + e < n) ? vin[c0 + e] * inv : 0.0;
-  // full tile columns and 16-byte aligned rows: vector loads; otherwise masked element loads
-  const bool vec = p.avec && (J * GEMV_TILE + GEMV_TILE <= n);
+  for (int e = 0; e < 4; ++e) {
+    const double v = vin[min(c0 + e, n - 1)];   // unconditional loads (no branch per load)
+    vj[e] = (c0 + e < n) ? v * inv : 0.0;
+  }
+  // v_I of row rw + lane (zero past n and on the diagonal tile, whose transpose is itself)
+  const double vr = vin[min(rw + lane, n - 1)];
+  const double vrow = (!diag && rw + lane < n) ? vr * inv : 0.0;
   double yc[4] = {0.0, 0.0, 0.0, 0.0};
   gmem<double>* __restrict__ gvp = gp(p.gvp);
-
-  // batch loads: rows r0 .. r0+RB-1 (clamped to n-1; rows past n are zeroed when used)
-  auto load = [&](T (&a)[RB][4], int r0) {
-    if (vec) {
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const gmem<const T>* src = A + (int64_t)min(r0 + q, n - 1) * lda + c0;
-        if constexpr (sizeof(T) == 4) {
-          const f32x4 x = __builtin_nontemporal_load((const gmem<f32x4>*)src);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) a[q][e] = x[e];
-        } else {
-          const f64x2 x0 = __builtin_nontemporal_load((const gmem<f64x2>*)src);
-          const f64x2 x1 = __builtin_nontemporal_load((const gmem<f64x2>*)(src + 2));
-          a[q][0] = x0[0]; a[q][1] = x0[1]; a[q][2] = x1[0]; a[q][3] = x1[1];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < RB; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          a[q][e] = (r0 + q < n && c0 + e < n) ? A[(int64_t)(r0 + q) * lda + c0 + e] : (T)0;
-    }
-  };
-  const int rw = I * GEMV_TILE + wave * 64;   // first row of this wave (wave-uniform)
-  T a[RB][4], an[RB][4];
-  if (rw < n) load(a, rw);
-#pragma unroll 1
-  for (int bt = 0; bt < 64 / RB; ++bt) {
-    const int r0 = rw + bt * RB;
-    if (r0 >= n) break;
-    if (bt + 1 < 64 / RB && r0 + RB < n) load(an, r0 + RB);
-    double rs[RB];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      // rows past n (clamped loads) contribute nothing
-      const bool ok = (r0 + q < n);
-      double x[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) x[e] = ok ? (double)a[q][e] : 0.0;
-      rs[q] = x[0] * vj[0] + x[1] * vj[1] + x[2] * vj[2] + x[3] * vj[3];
-      if (!diag) {
-        const double vi = ok ? vin[r0 + q] * inv : 0.0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) yc[e] += x[e] * vi;
-      }
-    }
-    reduce_scatter<RB>(rs, lane);
-    if ((lane & ((64 / RB) - 1)) == 0) {
-      const int rl = wave * 64 + bt * RB + (lane >> (6 - LOGRB));
-      gvp[((int64_t)I * nb + J) * GEMV_TILE + rl] = rs[0];
-    }
-#pragma unroll
-    for (int q = 0; q < RB; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) a[q][e] = an[q][e];
+  gmem<double>* __restrict__ rowout = gvp + ((int64_t)I * nb + J) * GEMV_TILE + wave * 64;
+  if (rw < n) {
+    const gmem<const T>* __restrict__ A = gp((const T*)p.A);
+    if (p.avec && J * GEMV_TILE + GEMV_TILE <= n)
+      gemv_stream<T, RB, true>(A, p.lda, n, rw, c0, vj, vrow, yc, rowout, lane);
+    else
+      gemv_stream<T, RB, false>(A, p.lda, n, rw, c0, vj, vrow, yc, rowout, lane);
   }
   // column sums: this wave's rows -> LDS, then the 4 waves in order
-  if (!diag) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) cred[wave][4 * lane + e] = yc[e];
-  }
+  for (int e = 0; e < 4; ++e) cred[wave][4 * lane + e] = yc[e];
   __syncthreads();
   if (!diag) {
     const int c = threadIdx.x;
