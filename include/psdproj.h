@@ -112,7 +112,8 @@ typedef struct {
 
 /* Where intermediate results live inside a run's workspace (byte offsets), for
  * inspection after the stream has passed the run.  Panels are column-major with
- * leading dimension panel_ld elements (column j of an n x r panel starts at j*panel_ld). */
+ * leading dimension panel_ld elements (column j of an n x r panel starts at j*panel_ld);
+ * panel_ld is a multiple of 128 and at least n + 32, and rows n .. panel_ld-1 hold zeros. */
 typedef struct {
     int32_t  r, r_pad, panel_ld, split_k;
     int32_t  panel_elem_bytes;  /* 8 (FP64) or 4 (FP32, BF16X3) */

@@ -11,6 +11,7 @@ namespace psd {
 typedef __bf16 bf16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 typedef __attribute__((ext_vector_type(2))) double f64x2;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
@@ -32,7 +33,8 @@ constexpr int PASS_BM_F = 256;                // rows per tile, FP32 / BF16X3 (8
 constexpr int PASS_BM_D = 64;                 // rows per tile, FP64 (16 per wave)
 constexpr int PASS_BK_F = 64;                 // K chunk granularity, FP32 / BF16X3
 constexpr int PASS_BK_D = 32;                 // K per LDS stage, FP64
-constexpr int PANEL_ALIGN = 64;               // panel leading dimension multiple
+constexpr int PANEL_TAIL = 32;                // zero rows past n in every panel: a pass step of K
+                                              // rows that starts before n stays inside the column
 constexpr int RPAD = 32;                      // panel column padding multiple
 constexpr int GRAM_TILE = 32;                 // Gram output tile
 constexpr int GRAM_CHUNK = 1024;              // rows per Gram partial
@@ -55,7 +57,7 @@ struct Prob {
   int32_t split, kchunk;           // pass split-K factor and chunk length
   int32_t ngchunk, alpha_iters;    // Gram row chunks, N of Alg. 4/5
   int32_t alpha_mode, rwpad;       // 0: alpha given (or plain), 1: estimate; rebuild-factor row stride
-  int32_t npass_tiles, avec;       // avec: rows of A start 16-byte aligned (vector loads allowed)
+  int32_t npass_tiles, avec;       // avec: rows of A start and end 16-byte aligned (vector loads)
   uint64_t seed;
   double alpha_in;
   const void* A; int64_t lda;

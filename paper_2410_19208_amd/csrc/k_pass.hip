@@ -8,20 +8,22 @@
 // same K chunk and that XCD's L2 holds only its 1/8 of Z.  Partials are summed in a fixed
 // order by k_pass_reduce, so results do not depend on scheduling.
 //
-// FP32 / BF16X3 (k_pass_lds): 8 waves own a 256-row tile and all r columns; each wave computes
-// a 64-row x r/2 block (4 x r/32 MFMA tiles), which balances the LDS bytes read per MFMA
-// between the A and Z operands.  Each K step of 32 moves the A slice (256 x 32 FP32) and the Z
-// slice (32 x r) from global memory straight into LDS (global_load_lds_dwordx4, no VGPR
-// round trip), double-buffered so the loads of step s+1 overlap the MFMAs of step s; one
-// barrier per step.  Slots inside each 1 KB block are XOR-swizzled so every 16-lane LDS read
-// of an MFMA operand touches 16 distinct 16-byte bank groups.
-//   FP32   -> v_mfma_f32_16x16x4f32;
-//   BF16X3 -> v_mfma_f32_16x16x32_bf16 on the splits x = hi + lo (hi = bf16(x),
-//             lo = bf16(x - hi)), accumulating hi*hi + hi*lo + lo*hi in FP32 (the lo*lo term,
-//             ~2^-16 relative, is dropped).  A is split in registers after the LDS read; Z is
-//             stored pre-split.
+// BF16X3 (k_pass_b3): v_mfma_f32_16x16x32_bf16 on the splits x = hi + lo (hi = bf16(x),
+// lo = bf16(x - hi)), accumulating hi*hi + hi*lo + lo*hi in FP32 (the lo*lo term, ~2^-16
+// relative, is dropped).  A is symmetric, so a tile's K slice is read as whole rows of A
+// (coalesced 1 KB rows), straight into registers in MFMA operand order and split there, two
+// steps ahead; Z is stored pre-split and its slices stream through a 3-slice LDS ring
+// (global_load_lds_dwordx4, no VGPR round trip).  8 waves x 32 rows x all r columns.
+// FP32 (k_pass_f32): 8 waves own a 256-row tile and all r columns; each wave computes a
+// 64-row x r/2 block (4 x r/32 MFMA tiles).  Each K step of 32 moves the A slice (256 x 32)
+// and the Z slice (32 x r) from global memory straight into LDS, double-buffered, one
+// barrier per step; v_mfma_f32_16x16x4f32 (this path is MFMA bound).  Slots inside each
+// 1 KB LDS block are XOR-swizzled so the 16-lane reads of an MFMA operand spread over the
+// banks.
 // FP64 (k_pass): 4 waves own a 64-row tile; A goes to registers in MFMA operand order, the
 // Z slice through LDS; v_mfma_f64_16x16x4f64 (this path is MFMA bound).
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -107,34 +109,31 @@ __global__ __launch_bounds__(PASS_THREADS, 2) void k_pass(const Prob* __restrict
   }
 }
 
-// ---------------------------------------------------------------- FP32 / BF16X3: LDS ring
+// ---------------------------------------------------------------- FP32: LDS ring
 constexpr int PL_THREADS = 512;                  // 8 waves: 4 row groups x 2 column halves
 constexpr int PL_BM = PASS_BM_F;                 // 256 rows per tile (64 per row group)
 constexpr int PL_BK = 32;                        // K per step
 constexpr int PL_ABYTES = PL_BM * PL_BK * 4;     // A slice: 32 blocks of 1 KB (8 rows each)
 
-// LDS bytes of one step: A slice + Z slice (2 KB per 16 columns: hi and lo, or FP32).
+// LDS bytes of one step: A slice + Z slice (2 KB per 16 columns).
 __host__ __device__ constexpr int pl_stage_bytes(int ncb) { return PL_ABYTES + ncb * 2048; }
 
 // Operand pointers and sizes of one pass, held in registers (the descriptor is read once).
 struct PlArgs {
   const float* A; int64_t lda;
-  const void* z0; const void* z1;   // BF16X3: hi, lo; FP32: the panel (z1 unused)
+  const float* z;
   int n, ld, avec;
 };
 
 // Issue the loads of step k0 into `stage`.
 //   A block b (rows 8b .. 8b+7 of the tile): row i at byte (i % 8) * 128, 16-byte slot s
 //     holds the 4 floats of chunk s ^ ((i % 16) / 2), i.e. columns k0 + 4c .. +3.
-//   Z, BF16X3: blocks 0..NCB-1 hold hi, NCB..2NCB-1 lo; block cb holds columns
-//     16cb .. 16cb+15 at 64 bytes each; slot s of column j holds chunk s ^ ((j % 16) / 4)
-//     (bf16 rows k0 + 8c .. +7).
-//   Z, FP32: block b holds columns 8b .. 8b+7 at 128 bytes each; slot s of column j holds
-//     chunk s ^ ((j % 16) / 2) (rows k0 + 4c .. +3).
+//   Z: block b holds columns 8b .. 8b+7 at 128 bytes each; slot s of column j holds chunk
+//     s ^ ((j % 16) / 2) (rows k0 + 4c .. +3).
 // A rows past n are clamped to n - 1 (their outputs are never stored); A chunks starting at or
 // past n read the row's first chunk instead and are zeroed after the LDS read.  Z rows in
-// [n, ld) are zero in every panel.
-template <int PREC, int NCB>
+// [n, ld) are zero in every panel, and ld >= n + 32.
+template <int NCB>
 __device__ __forceinline__ void pl_issue(const PlArgs& g, unsigned char* stage, int m0, int k0, int wave,
                                          int lane) {
   const int n = g.n;
@@ -169,23 +168,14 @@ __device__ __forceinline__ void pl_issue(const PlArgs& g, unsigned char* stage, 
   for (int u = 0; u < (2 * NCB + 7) / 8; ++u) {
     const int b = wave + 8 * u;
     if (b >= 2 * NCB) break;
-    if constexpr (PREC == B3) {
-      const bf16* z = (const bf16*)((b < NCB) ? g.z0 : g.z1);
-      const int cb = (b < NCB) ? b : b - NCB;
-      const int j = lane >> 2;
-      const int c = (lane & 3) ^ (j >> 2);
-      dma16(z + (int64_t)(cb * 16 + j) * g.ld + k0 + 8 * c, zs + b * 1024);
-    } else {
-      const float* z = (const float*)g.z0;
-      const int col = b * 8 + (lane >> 3);
-      const int c = (lane & 7) ^ ((col & 15) >> 1);
-      dma16(z + (int64_t)col * g.ld + k0 + 4 * c, zs + b * 1024);
-    }
+    const int col = b * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((col & 15) >> 1);
+    dma16(g.z + (int64_t)col * g.ld + k0 + 4 * c, zs + b * 1024);
   }
 }
 
 // MFMAs of one step.  Lane (li, kg) of an operand holds K indices 8kg .. 8kg+7 of the step.
-template <int PREC, int NCB>
+template <int NCB>
 __device__ __forceinline__ void pl_compute(const unsigned char* stage, int wr, int wc, int lane, int kvalid,
                                            f32x4 (&acc)[4][NCB / 2]) {
   constexpr int NCH = NCB / 2;
@@ -209,34 +199,7 @@ __device__ __forceinline__ void pl_compute(const unsigned char* stage, int wr, i
         if (8 * kg + 4 + e >= kvalid) a1[rb][e] = 0.0f;
       }
   }
-  if constexpr (PREC == B3) {
-    bf16x8 ahi[4], alo[4];
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float x = (e < 4) ? a0[rb][e] : a1[rb][e - 4];
-        const bf16 h = (bf16)x;
-        ahi[rb][e] = h;
-        alo[rb][e] = (bf16)(x - (float)h);
-      }
-    const int zoff = li * 64 + ((kg ^ (li >> 2)) << 4);
-#pragma unroll
-    for (int cb = 0; cb < NCH; ++cb) {
-      const int gcb = wc * NCH + cb;
-      const bf16x8 bhi = *(const bf16x8*)(zs + gcb * 1024 + zoff);
-      const bf16x8 blo = *(const bf16x8*)(zs + (NCB + gcb) * 1024 + zoff);
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], bhi, acc[rb][cb], 0, 0, 0);
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[rb], blo, acc[rb][cb], 0, 0, 0);
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[rb], bhi, acc[rb][cb], 0, 0, 0);
-    }
-  } else {
+  {
     const int zoff0 = (li & 7) * 128 + (((2 * kg) ^ (li >> 1)) << 4);
     const int zoff1 = (li & 7) * 128 + (((2 * kg + 1) ^ (li >> 1)) << 4);
 #pragma unroll
@@ -258,8 +221,8 @@ __device__ __forceinline__ void pl_compute(const unsigned char* stage, int wr, i
   }
 }
 
-template <int PREC, int NCB>
-__global__ __launch_bounds__(PL_THREADS, 1) void k_pass_lds(const Prob* __restrict__ probs,
+template <int NCB>
+__global__ __launch_bounds__(PL_THREADS, 1) void k_pass_f32(const Prob* __restrict__ probs,
                                                            const int* __restrict__ tstart, int nprob) {
   static_assert(NCB % 2 == 0, "panel widths are multiples of 32 columns");
   constexpr int NCH = NCB / 2;
@@ -287,20 +250,19 @@ __global__ __launch_bounds__(PL_THREADS, 1) void k_pass_lds(const Prob* __restri
 
   PlArgs g;
   g.A = (const float*)p.A; g.lda = p.lda;
-  g.z0 = (PREC == B3) ? (const void*)p.zhi : p.zm;
-  g.z1 = (PREC == B3) ? (const void*)p.zlo : p.zm;
+  g.z = (const float*)p.zm;
   g.n = n; g.ld = ld; g.avec = p.avec;
   float* __restrict__ out = (float*)p.part + (int64_t)s * p.rpad * ld;
 
-  pl_issue<PREC, NCB>(g, smem, m0, kbeg, wave, lane);
+  pl_issue<NCB>(g, smem, m0, kbeg, wave, lane);
   for (int st = 0; st < nsteps; ++st) {
     // this wave's loads of step st have landed; the barrier publishes everyone's, and also
     // ends every wave's reads of the other buffer (step st - 1), which step st + 1 overwrites
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     __syncthreads();
     const int k0 = kbeg + st * PL_BK;
-    if (st + 1 < nsteps) pl_issue<PREC, NCB>(g, smem + ((st + 1) & 1) * SB, m0, k0 + PL_BK, wave, lane);
-    pl_compute<PREC, NCB>(smem + (st & 1) * SB, wr, wc, lane, kend - k0, acc);
+    if (st + 1 < nsteps) pl_issue<NCB>(g, smem + ((st + 1) & 1) * SB, m0, k0 + PL_BK, wave, lane);
+    pl_compute<NCB>(smem + (st & 1) * SB, wr, wc, lane, kend - k0, acc);
   }
 
   // ---- partial tile: lane (li, kg) holds rows 4kg .. 4kg+3 of block (rb, cb), column li
@@ -315,6 +277,218 @@ __global__ __launch_bounds__(PL_THREADS, 1) void k_pass_lds(const Prob* __restri
       *(f32x4*)dst = acc[rb][cb];
     }
   }
+}
+
+// ---------------------------------------------------------------- BF16X3: A read transposed
+// A is symmetric, so a tile's K slice of A can be read as whole rows of A: the 256 output rows
+// m0 .. m0+255 of the tile are 256 consecutive columns of A, and step k0 reads rows
+// k0 .. k0+31 of A over those columns (1 KB per row; reading 128 bytes from each of 256 rows
+// instead streams markedly slower).  Wave w owns output rows m0 + 32w .. +31 and every column
+// of the panel.  Lane (li, kg) loads, for e = 0..7, the two floats of row k0 + 8kg + e at
+// columns m0 + 32w + 2li, +1: for v = 0, 1 the eight values of column m0 + 32w + 2li + v are
+// the MFMA A operand (K = 8kg .. 8kg+7) of row li of "virtual" row block v, whose 16 rows are
+// m0 + 32w + 2i + v.  So A never passes through LDS: it is loaded PB_DIST steps ahead into a
+// register ring, and only the Z slices (shared by the 8 waves) stream through a ring of
+// PB_DIST + 1 LDS slices.
+// VB = 2 virtual row blocks per wave (8 waves, two per SIMD).  Four (4 waves, one per SIMD,
+// halving the LDS reads of Z) would need more than the register file with a 3-slot ring.
+constexpr int PB_VB = 2;
+constexpr int PB_BK = 32;
+constexpr int PB_DIST = 2;                       // steps in flight ahead of the one computed
+constexpr int PB_RING = PB_DIST + 1;
+__host__ __device__ constexpr int pb_slice_bytes(int ncb) { return ncb * 2048; }   // hi + lo
+__host__ __device__ constexpr int pb_lds_bytes(int ncb) { return PB_RING * pb_slice_bytes(ncb); }
+// Z blocks (1 KB) per wave and step: wave w issues blocks w, w + 8, ... mod 2 ncb, so every
+// wave issues the same number of loads (a repeated block rewrites the same bytes)
+__host__ __device__ constexpr int pb_zpw(int ncb) { return (2 * ncb + 7) / 8; }
+
+// Z slice layout: block b (1 KB) holds columns 16cb .. 16cb+15 of hi (b = cb) or lo
+// (b = NCB + cb), 64 bytes (32 K values) per column; slot s of column j holds the K chunk
+// s ^ pb_swz(j).  The swizzle gives distinct bank groups to every 8 and every 16 consecutive
+// lanes of an operand read (lane (li, kg) reads chunk kg of column li).
+__device__ __forceinline__ int pb_swz(int j) { return ((j >> 1) ^ (j >> 3)) & 3; }
+
+// s_waitcnt with vmcnt = N (0..63), lgkmcnt = 0, expcnt unchanged
+#define PB_VMCNT(N) (0x0070 | ((N) & 15) | (((N) >> 4) << 14))
+
+template <int VB> struct PbVec;
+template <> struct PbVec<2> { using T = f32x2; };
+template <> struct PbVec<4> { using T = f32x4; };
+
+// One tile, VB virtual row blocks per wave (256 / (16 VB) waves).  AVEC: 16-byte aligned rows
+// and n % 4 == 0 (A as VB-float loads; such a group of columns is wholly inside or wholly
+// past column n); otherwise element loads at clamped addresses, and every step waits for all
+// of its loads.
+template <int NCB, int VB, bool AVEC>
+__device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char* smem) {
+  using VT = typename PbVec<VB>::T;
+  constexpr int NW = PASS_BM_F / (16 * VB);       // waves
+  constexpr int SB = pb_slice_bytes(NCB);
+  constexpr int ZPW = (2 * NCB + NW - 1) / NW;    // Z blocks per wave and step
+  constexpr int LPS = AVEC ? 8 + ZPW : 0;         // loads per wave and step
+  const int s = t % p.split;
+  const int m0 = (t / p.split) * PASS_BM_F;
+  const int n = p.n, ld = p.ld;
+  const int kbeg = s * p.kchunk;
+  const int kend = min(n, kbeg + p.kchunk);
+  const int nsteps = (kend - kbeg + PB_BK - 1) / PB_BK;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int li = lane & 15, kg = lane >> 4;
+  const gmem<const bf16>* __restrict__ zhi = gp((const bf16*)p.zhi);
+  const gmem<const bf16>* __restrict__ zlo = gp((const bf16*)p.zlo);
+  const gmem<const float>* __restrict__ A = gp((const float*)p.A);
+  const int64_t lda = p.lda;
+  // first of this lane's VB columns (a group past n reads column 0 instead: its outputs are
+  // rows past n, never stored)
+  const int mc = m0 + 16 * VB * wave + VB * li;
+  const int mcol = (mc < n) ? mc : 0;
+
+  VT ar[PB_RING][8];         // A of the steps in flight: [ring slot][e]
+  f32x4 acc[VB][NCB];
+#pragma unroll
+  for (int v = 0; v < VB; ++v)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[v][cb] = f32x4{0, 0, 0, 0};
+
+  // loads of step st into ring slot S.  Steps past the last one load the last step again (a
+  // slot nobody reads), and rows at or past the chunk end read row kbeg (zeroed at use), so
+  // every step issues the same loads and the compiler's wait counts stay exact.
+  auto issue = [&](auto S_, int st) {
+    constexpr int S = decltype(S_)::value;
+    const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + 8 * kg + e;
+      const int64_t row = (int64_t)((k < kend) ? k : kbeg) * lda;
+      if constexpr (AVEC) {
+        ar[S][e] = __builtin_nontemporal_load((const gmem<VT>*)(A + row + mcol));
+      } else {
+#pragma unroll
+        for (int q = 0; q < VB; ++q) ar[S][e][q] = A[row + min(mc + q, n - 1)];
+      }
+    }
+    unsigned char* zs = smem + S * SB;
+    const int j = lane >> 2;
+    const int c = (lane & 3) ^ pb_swz(j);
+#pragma unroll
+    for (int u = 0; u < ZPW; ++u) {
+      const int b = (wave + NW * u) % (2 * NCB);
+      const gmem<const bf16>* z = (b < NCB) ? zhi : zlo;
+      const int cb = (b < NCB) ? b : b - NCB;
+      dma16((const void*)(z + (int64_t)(cb * 16 + j) * ld + k0 + 8 * c), zs + b * 1024);
+    }
+  };
+
+  // wait until this wave's loads of step st have landed (and its LDS reads of step st - 1 are
+  // done): the only loads issued later are those of step st + 1.  Then a bare barrier: a
+  // workgroup fence would also wait for the loads in flight for step st + 1 (LDS-DMA writes
+  // count as vector memory operations).
+  auto wait_step = [&]() {
+    __builtin_amdgcn_s_waitcnt(PB_VMCNT(LPS));
+    __asm__ volatile("s_barrier" ::: "memory");
+  };
+
+  const int zoff = li * 64 + ((kg ^ pb_swz(li)) << 4);
+  auto compute = [&](auto S_, int st) {
+    constexpr int S = decltype(S_)::value;
+    const int kvalid = kend - (kbeg + st * PB_BK);
+    bf16x8 ahi[VB], alo[VB];
+#pragma unroll
+    for (int v = 0; v < VB; ++v)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float x = ar[S][e][v];
+        if (kvalid < PB_BK && 8 * kg + e >= kvalid) x = 0.0f;
+        const bf16 hb = (bf16)x;
+        ahi[v][e] = hb;
+        alo[v][e] = (bf16)(x - (float)hb);
+      }
+    // widths 12 and 16: split before any MFMA of the step (interleaving the two runs out of
+    // registers there); elsewhere the interleaved schedule fits and is faster
+    if constexpr (NCB == 12 || NCB == 16) __builtin_amdgcn_sched_barrier(0);
+    const unsigned char* zs = smem + S * SB;
+    // column blocks in pairs: 2 VB independent accumulators between dependent MFMAs
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb += 2) {
+      const bf16x8 h0 = *(const bf16x8*)(zs + cb * 1024 + zoff);
+      const bf16x8 h1 = *(const bf16x8*)(zs + (cb + 1) * 1024 + zoff);
+      const bf16x8 l0 = *(const bf16x8*)(zs + (NCB + cb) * 1024 + zoff);
+      const bf16x8 l1 = *(const bf16x8*)(zs + (NCB + cb + 1) * 1024 + zoff);
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], h0, acc[v][cb], 0, 0, 0);
+        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], h1, acc[v][cb + 1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], l0, acc[v][cb], 0, 0, 0);
+        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], l1, acc[v][cb + 1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[v], h0, acc[v][cb], 0, 0, 0);
+        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[v], h1, acc[v][cb + 1], 0, 0, 0);
+      }
+    }
+  };
+
+  // one step in ring slot S (= st mod PB_RING): its loads landed everywhere (the barrier also
+  // ends every wave's reads of step st - 1, whose slot step st + PB_DIST overwrites), issue
+  // step st + PB_DIST, compute step st
+  auto step = [&](auto S_, int st) {
+    constexpr int S = decltype(S_)::value;
+    wait_step();
+    issue(std::integral_constant<int, (S + PB_DIST) % PB_RING>{}, st + PB_DIST);
+    compute(S_, st);
+  };
+
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  static_assert(PB_RING == 3, "the step loop below is unrolled for a ring of three");
+  issue(S0{}, 0);
+  issue(S1{}, 1);
+  int st = 0;
+  for (; st + 3 <= nsteps; st += 3) {
+    step(S0{}, st);
+    step(S1{}, st + 1);
+    step(S2{}, st + 2);
+  }
+  if (st < nsteps) step(S0{}, st);
+  if (st + 1 < nsteps) step(S1{}, st + 1);
+  // the repeated loads of the steps past the end must land before the workgroup's LDS is freed
+  __builtin_amdgcn_s_waitcnt(PB_VMCNT(0));
+
+  // ---- partial tile.  Lane (li, kg) of acc[v][cb] holds rows 4kg + r (r = 0..3) of virtual
+  // block v, column li: output row m0 + 16 VB wave + VB (4 kg + r) + v, so the lane holds the
+  // 4 VB consecutive rows from m0 + 16 VB wave + 4 VB kg (VB 16-byte stores per column).
+  float* __restrict__ out = (float*)p.part + (int64_t)s * p.rpad * ld;
+  const int rbase = m0 + 16 * VB * wave + 4 * VB * kg;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    float vals[4 * VB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int v = 0; v < VB; ++v) vals[VB * r + v] = acc[v][cb][r];
+    float* col = out + (int64_t)(cb * 16 + li) * ld + rbase;
+#pragma unroll
+    for (int h = 0; h < VB; ++h)
+      if (rbase + 4 * h < n) *(f32x4*)(col + 4 * h) = f32x4{vals[4 * h], vals[4 * h + 1], vals[4 * h + 2], vals[4 * h + 3]};
+  }
+}
+
+template <int NCB, int VB>
+__global__ __launch_bounds__(PASS_BM_F / (16 * VB) * 64, 1)
+void k_pass_b3(const Prob* __restrict__ probs, const int* __restrict__ tstart, int nprob) {
+  static_assert(NCB % 2 == 0, "panel widths are multiples of 32 columns");
+  extern __shared__ __attribute__((aligned(1024))) unsigned char smem[];
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int t = blockIdx.x - tstart[pi];
+  if (t >= p.npass_tiles) return;
+  if (p.avec) pass_b3_tile<NCB, VB, true>(p, t, smem);
+  else pass_b3_tile<NCB, VB, false>(p, t, smem);
 }
 
 // Y = sum_s part[s] in fixed order; scaled: Y = (Y + alpha Z) / alpha.  Zero outside n x r.
@@ -371,10 +545,11 @@ void launch_pass(const Launch& L, int prec, int ncb) {
 #define PSD_CASE(N)                                                                                              \
   case N:                                                                                                        \
     if (prec == F32)                                                                                             \
-      hipLaunchKernelGGL((k_pass_lds<F32, N>), dim3(L.grid), dim3(PL_THREADS), 2 * pl_stage_bytes(N), L.stream, \
+      hipLaunchKernelGGL((k_pass_f32<N>), dim3(L.grid), dim3(PL_THREADS), 2 * pl_stage_bytes(N), L.stream, \
                          L.probs, L.tstart, L.nprob);                                                            \
     else                                                                                                         \
-      hipLaunchKernelGGL((k_pass_lds<B3, N>), dim3(L.grid), dim3(PL_THREADS), 2 * pl_stage_bytes(N), L.stream,  \
+      hipLaunchKernelGGL((k_pass_b3<N, PB_VB>), dim3(L.grid), dim3(PASS_BM_F / (16 * PB_VB) * 64),               \
+                         pb_lds_bytes(N), L.stream,                                                              \
                          L.probs, L.tstart, L.nprob);                                                            \
     break;
     PSD_NCB_EVEN(PSD_CASE)
@@ -386,10 +561,10 @@ void launch_pass(const Launch& L, int prec, int ncb) {
 // Opt the LDS-ring pass kernels into more than 64 KB of dynamic LDS.
 void pass_init() {
 #define PSD_ATTR(N)                                                                                    \
-  hipFuncSetAttribute((const void*)k_pass_lds<F32, N>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+  hipFuncSetAttribute((const void*)k_pass_f32<N>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
                       2 * pl_stage_bytes(N));                                                          \
-  hipFuncSetAttribute((const void*)k_pass_lds<B3, N>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
-                      2 * pl_stage_bytes(N));
+  hipFuncSetAttribute((const void*)k_pass_b3<N, PB_VB>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                      pb_lds_bytes(N));
   PSD_NCB_EVEN(PSD_ATTR)
 #undef PSD_ATTR
 }

@@ -40,7 +40,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   const int n = (int)d->n;
   pl.r = (int)r;
   pl.rpad = rup(pl.r, RPAD);
-  pl.ld = rup(n, 128);
+  pl.ld = rup(n + PANEL_TAIL, 128);
   pl.prec = d->precision;
   pl.es = (pl.prec == F64) ? 8 : 4;
   pl.ncb = pl.rpad / 16;
@@ -113,7 +113,9 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   p.alpha_iters = d.alpha_iters; p.alpha_mode = pl.alpha_mode; p.rwpad = pl.rwpad;
   p.seed = d.seed; p.alpha_in = d.alpha;
   p.A = A; p.lda = lda; p.P = P; p.ldp = ldp;
-  p.avec = ((lda * pl.es) % 16 == 0) ? 1 : 0;
+  // 16-byte loads of A: rows start 16-byte aligned and end on a 16-byte boundary, so an
+  // aligned 16-byte chunk of a row lies wholly inside or wholly past column n
+  p.avec = ((lda * pl.es) % 16 == 0 && (d.n * pl.es) % 16 == 0) ? 1 : 0;
   auto at = [&](size_t off) { return (void*)(region + off); };
   p.zm = at(pl.o_zm);
   p.zhi = (bf16*)(pl.prec == B3 ? at(pl.o_zhi) : nullptr);
