@@ -24,13 +24,13 @@
  *   current HIP device.  Plans and servers are library-owned opaque handles.  A must stay
  *   valid and unchanged until the stream has passed the call (or the ticket completed).
  *   A must be exactly symmetric (the method projects a symmetric matrix, Sec. 2).  The passes
- *   of Alg. 1-3 read it in full; the power iterations of Alg. 4/5 read only its upper
- *   triangle and diagonal.  Row- and column-major are the same for a symmetric matrix;
- *   element (i, j) is at A[i * lda + j].
+ *   of Alg. 1-3 read it in full (the BF16X3 pass reads A's rows as the columns of A^T = A);
+ *   the power iterations of Alg. 4/5 read only its upper triangle and diagonal.  Row- and
+ *   column-major are the same for a symmetric matrix; element (i, j) is at A[i * lda + j].
  *   Precision FP64: A and P hold double.  FP32 and BF16X3: A and P hold float.
  *   Requirements: lda >= n, ldp >= n, A and P 16-byte aligned.  When lda * sizeof(element)
- *   is a multiple of 16 the passes over A use 16-byte vector loads; otherwise they fall back
- *   to element loads (correct, slower).  P may alias A exactly (same pointer and ld): the
+ *   and n * sizeof(element) are multiples of 16 the passes over A use vector loads;
+ *   otherwise they fall back to element loads (correct, slower).  P may alias A exactly (same pointer and ld): the
  *   rebuild runs after the last read of A.  Any other overlap is E_INVALID.
  *
  * Errors
