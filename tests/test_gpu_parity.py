@@ -72,14 +72,15 @@ def test_parity_ragged(prec, variant, alpha, q):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("variant,alpha", [("plain", 0.0), ("scaled", 0.0)])
-@pytest.mark.parametrize("lda", [780, 800])
-def test_parity_ragged_padded_rows(prec, variant, alpha, lda):
-    """n = 777 stored in a wider buffer (row stride lda, 16-byte aligned rows) whose padding
-    columns hold NaN: the ragged last tile and K step must never let them into the result."""
+@pytest.mark.parametrize("n,lda", [(777, 780), (777, 800), (780, 800)])
+def test_parity_ragged_padded_rows(prec, variant, alpha, n, lda):
+    """n stored in a wider buffer (row stride lda, 16-byte aligned rows) whose padding columns
+    hold NaN: the ragged last tile and K step must never let them into the result.  n = 777
+    takes the element-load path, n = 780 (a multiple of 4) the vector-load path."""
     import torch
     from paper_2410_19208_amd.torch_api import Projector
     dev = _gpu.device()
-    n, k, p, q = 777, 40, 12, 1
+    k, p, q = 40, 12, 1
     A, lam, U = matrix("medium", n, 5, n_pos=60)
     dt = torch.float64 if prec == "fp64" else torch.float32
     buf = torch.full((n, lda), float("nan"), dtype=dt, device=dev)
@@ -90,7 +91,7 @@ def test_parity_ragged_padded_rows(prec, variant, alpha, lda):
     ref = run_oracle(A, k, p, q, variant, prec, seed=3, alpha=alpha)
     assert res.status == 0
     err = parity(P, ref, A)
-    print(f"padded lda={lda} {prec} {variant}: parity {err:.3e}")
+    print(f"padded n={n} lda={lda} {prec} {variant}: parity {err:.3e}")
     assert err < TOL[prec]
 
 
