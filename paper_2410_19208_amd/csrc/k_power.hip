@@ -108,17 +108,20 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __rest
 
 // Stream one wave's 64 rows of a tile in batches of RB rows, double-buffered in registers (the
 // loop is fully unrolled, so the loads of batch bt+1 are in flight while batch bt is used and
-// no copy between the buffers forces an early wait).  VEC: full tile columns and 16-byte
-// aligned rows, one 16-byte load per row and lane; otherwise element loads at clamped
-// addresses with the values past column n zeroed.  Rows past n are loaded clamped to row
-// n-1; their row sums land in partial slots that are never read and their column terms are
-// multiplied by a zero v_I.
+// no copy between the buffers forces an early wait).  VEC: rows start and end 16-byte aligned,
+// so a 16-byte chunk lies wholly inside or wholly past column n; chunks past n read the row's
+// first chunk instead (their v_J entries are zero, and their column sums belong to columns
+// past n, never read).  Otherwise element loads at clamped addresses with the values past
+// column n zeroed.  Rows past n are loaded clamped to row n-1; their row sums land in partial
+// slots that are never read and their column terms are multiplied by a zero v_I.
+// The vector entries are waited for only once two batches of A are in flight, so the tile's
+// stream starts without waiting for them.
 template <typename T, int RB, bool VEC>
 __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A, int64_t lda, int n, int rw, int c0,
-                                            const double (&vj)[4], double vrow, double (&yc)[4],
-                                            gmem<double>* __restrict__ rowout, int lane) {
+                                            const gmem<const double>* __restrict__ vin, double inv, bool diag,
+                                            double (&yc)[4], gmem<double>* __restrict__ rowout, int lane) {
   constexpr int NBT = 64 / RB;
-  constexpr int LOGRB = (RB == 16) ? 4 : 3;
+  constexpr int LOGRB = (RB == 16) ? 4 : (RB == 8) ? 3 : 2;
   T a[2][RB][4];
   auto load = [&](T (&dst)[RB][4], int r0) {
 #pragma unroll
@@ -126,12 +129,12 @@ __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A,
       const int64_t row = (int64_t)min(r0 + q, n - 1) * lda;
       if constexpr (VEC) {
         if constexpr (sizeof(T) == 4) {
-          const f32x4 x = __builtin_nontemporal_load((const gmem<f32x4>*)(A + row + c0));
+          const f32x4 x = __builtin_nontemporal_load((const gmem<f32x4>*)(A + row + (c0 < n ? c0 : 0)));
 #pragma unroll
           for (int e = 0; e < 4; ++e) dst[q][e] = x[e];
         } else {
-          const f64x2 x0 = __builtin_nontemporal_load((const gmem<f64x2>*)(A + row + c0));
-          const f64x2 x1 = __builtin_nontemporal_load((const gmem<f64x2>*)(A + row + c0 + 2));
+          const f64x2 x0 = __builtin_nontemporal_load((const gmem<f64x2>*)(A + row + (c0 < n ? c0 : 0)));
+          const f64x2 x1 = __builtin_nontemporal_load((const gmem<f64x2>*)(A + row + (c0 + 2 < n ? c0 + 2 : 0)));
           dst[q][0] = x0[0]; dst[q][1] = x0[1]; dst[q][2] = x1[0]; dst[q][3] = x1[1];
         }
       } else {
@@ -143,12 +146,26 @@ __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A,
       }
     }
   };
+  // raw vector entries (unconditional loads, no branch per load), used only once two batches
+  // of A are in flight
+  double vjr[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) vjr[e] = vin[min(c0 + e, n - 1)];
+  const double vrr = vin[min(rw + lane, n - 1)];
   load(a[0], rw);
+  double vj[4], vrow = 0.0;
 #pragma unroll
   for (int bt = 0; bt < NBT; ++bt) {
     // keep the scheduler from hoisting later batches' loads (they would need more buffers)
     __builtin_amdgcn_sched_barrier(0);
     if (bt + 1 < NBT) load(a[(bt + 1) & 1], rw + (bt + 1) * RB);
+    if (bt == 0) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) vj[e] = (c0 + e < n) ? vjr[e] * inv : 0.0;
+      // v_I of row rw + lane (zero past n and on the diagonal tile, whose transpose is itself)
+      vrow = (!diag && rw + lane < n) ? vrr * inv : 0.0;
+    }
     double rs[RB];
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
@@ -170,7 +187,8 @@ __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A,
   }
 }
 
-// RB rows per load batch: 16 for FP32 storage, 8 for FP64 (64 VGPRs of A per buffer).
+// RB rows per load batch: 8 for FP32 storage, 4 for FP64 (32 VGPRs of A per buffer, so the
+// kernel keeps 3 waves per SIMD).
 template <typename T, int RB>
 __device__ __forceinline__ void gemv_tile(const Prob& p, int t) {
   const int n = p.n, ld = p.ld;
@@ -187,29 +205,21 @@ __device__ __forceinline__ void gemv_tile(const Prob& p, int t) {
   // lane owns columns c0 .. c0+3 of the tile, the wave rows rw .. rw+63
   const int c0 = J * GEMV_TILE + 4 * lane;
   const int rw = I * GEMV_TILE + wave * 64;
-  double vj[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const double v = vin[min(c0 + e, n - 1)];   // unconditional loads (no branch per load)
-    vj[e] = (c0 + e < n) ? v * inv : 0.0;
-  }
-  // v_I of row rw + lane (zero past n and on the diagonal tile, whose transpose is itself)
-  const double vr = vin[min(rw + lane, n - 1)];
-  const double vrow = (!diag && rw + lane < n) ? vr * inv : 0.0;
   double yc[4] = {0.0, 0.0, 0.0, 0.0};
   gmem<double>* __restrict__ gvp = gp(p.gvp);
   gmem<double>* __restrict__ rowout = gvp + ((int64_t)I * nb + J) * GEMV_TILE + wave * 64;
   if (rw < n) {
     const gmem<const T>* __restrict__ A = gp((const T*)p.A);
-    if (p.avec && J * GEMV_TILE + GEMV_TILE <= n)
-      gemv_stream<T, RB, true>(A, p.lda, n, rw, c0, vj, vrow, yc, rowout, lane);
+    if (p.avec)
+      gemv_stream<T, RB, true>(A, p.lda, n, rw, c0, vin, inv, diag, yc, rowout, lane);
     else
-      gemv_stream<T, RB, false>(A, p.lda, n, rw, c0, vj, vrow, yc, rowout, lane);
+      gemv_stream<T, RB, false>(A, p.lda, n, rw, c0, vin, inv, diag, yc, rowout, lane);
   }
-  // column sums: this wave's rows -> LDS, then the 4 waves in order
+  // column sums: this wave's rows -> LDS, then the 4 waves in order (an LDS-only barrier: the
+  // row-sum stores need not land first)
 #pragma unroll
   for (int e = 0; e < 4; ++e) cred[wave][4 * lane + e] = yc[e];
-  __syncthreads();
+  lds_barrier();
   if (!diag) {
     const int c = threadIdx.x;
     gvp[((int64_t)J * nb + I) * GEMV_TILE + c] = cred[0][c] + cred[1][c] + cred[2][c] + cred[3][c];
@@ -221,8 +231,8 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv(const Prob* __restrict__ 
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int t = blockIdx.x - tstart[pi];
-  if (p.prec == F64) gemv_tile<double, 8>(p, t);
-  else gemv_tile<float, 16>(p, t);
+  if (p.prec == F64) gemv_tile<double, 4>(p, t);
+  else gemv_tile<float, 8>(p, t);
 }
 
 // alpha = |sigma1 - sigma2| (Alg. 5 line 4); E_ALPHA unless positive and finite.
