@@ -31,6 +31,33 @@ BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large_20k_bf16x3.md")
+
+
+def measured_traffic(kernel: str, problems_per_launch: float):
+    """HBM bytes per launch (read + written) of `kernel` from the counter summary in profiles/:
+    FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy.  None when there is no entry, when the
+    launch covers a different number of problems, or when the kernel's source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        ent = json.loads(block).get(kernel)
+        if ent is None or abs(ent["problems_per_launch"] - problems_per_launch) > 1e-9:
+            return None
+        with open(os.path.join(ROOT, ent["source"]), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != ent["sha1"]:
+                return None
+        return float(ent["read_bytes"] + ent["write_bytes"])
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+
+
+def rnd(x, nd):
+    return None if x is None else round(x, nd)
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -49,11 +76,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (parity and CPU timing)")
     ap.add_argument("--no-fp32-compare", action="store_true", help="skip timing the plain FP32 form")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-side-timings", action="store_true",
+                    help="skip the untimed single-request and sequential/grouped comparison timings "
+                         "(profiler runs: only warmup and timed steps launch kernels)")
     ap.add_argument("--sequential", action="store_true",
                     help="time the step as two psdproj_run calls instead of one grouped psdproj_batch")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve"],
+    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "counters"],
                     help="step: the headline n=20000 step (default); batch: 256 uneven problems in one "
-                         "grouped launch sequence; serve: Poisson arrivals through the request server")
+                         "grouped launch sequence; serve: Poisson arrivals through the request server; "
+                         "counters: a short run for hardware-counter profiles (symmetric Gaussian A, no QR "
+                         "in the generator, two grouped steps, then one 1 GiB device copy for calibration)")
     ap.add_argument("--qps", default="50,100,200,500,1000,2000", help="serve mode: arrival rates")
     ap.add_argument("--serve-requests", type=int, default=400, help="serve mode: requests per rate (at most)")
     return ap.parse_args()
@@ -82,6 +114,8 @@ def main() -> int:
         return run_batch(args, dev)
     if args.mode == "serve":
         return run_serve(args, dev)
+    if args.mode == "counters":
+        return run_counters(args, dev)
     n, k, p, q = args.n, args.k, args.p, args.q
     r = k + p
 
@@ -151,17 +185,19 @@ def main() -> int:
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t) / reps
 
-    ms_plain = one(plain, P1)
-    ms_scaled = one(scaled, P2)
-    other = step_grouped if args.sequential else step_sequential
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(3):
-        other()
-    torch.cuda.synchronize()
-    ms_other = 1e3 * (time.perf_counter() - t) / 3
-    step()
-    torch.cuda.synchronize()
+    ms_plain = ms_scaled = ms_other = None
+    if not args.no_side_timings:
+        ms_plain = one(plain, P1)
+        ms_scaled = one(scaled, P2)
+        other = step_grouped if args.sequential else step_sequential
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            other()
+        torch.cuda.synchronize()
+        ms_other = 1e3 * (time.perf_counter() - t) / 3
+        step()
+        torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- algorithmic work
     es = 8 if args.precision == "fp64" else 4
@@ -199,10 +235,25 @@ def main() -> int:
         note = "no algorithmic byte model for this kernel"
     alg = per_unit * units / launches_per_step
     achieved = alg / (d["avg_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(dom, units / launches_per_step)
     roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "algorithmic_bytes_per_launch": alg,
+                "frac": round(achieved / peak, 4), "traffic": traffic, "algorithmic_bytes_per_launch": alg,
                 "problems_per_launch": round(units / launches_per_step, 3),
                 "avg_launch_us": round(d["avg_us"], 2), "model": note}
+
+    # every A-streaming kernel against the HBM roofline (algorithmic bytes per launch)
+    streaming = {}
+    for kname, per, units_step in (("k_pass", nn * es, 2 * passes),
+                                   ("k_gemv", n * (n + 1) / 2 * es + 2 * n * 8.0, 2 * (args.alpha_iters + 1)),
+                                   ("k_rebuild", nn * es, 2)):
+        if kname in kern:
+            kd = kern[kname]
+            lps = kd["launches"] / args.steps
+            b = per * units_step / lps
+            gbs = b / (kd["avg_us"] * 1e-6) / 1e9
+            streaming[kname] = {"gb_per_launch": round(b / 1e9, 4), "avg_us": round(kd["avg_us"], 2),
+                                "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                                "traffic_bytes": measured_traffic(kname, units_step / lps)}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "projections/s", "n_gpus": 1, "steps": args.steps,
@@ -212,17 +263,18 @@ def main() -> int:
                                f"alpha by Alg. 5 with N={args.alpha_iters}) projection per step; A fp32 resident",
                    "n": n, "k": k, "p": p, "q": q, "precision": args.precision,
                    "step": "two psdproj_run calls" if args.sequential else "one grouped psdproj_batch of both"},
-        "ms_per_step_" + ("grouped" if args.sequential else "sequential"): round(ms_other, 4),
+        "ms_per_step_" + ("grouped" if args.sequential else "sequential"): rnd(ms_other, 4),
         "tflops": round(tflops, 2), "hbm_gbs": round(gbs, 1),
-        "latency_ms": {"plain": round(ms_plain, 3), "scaled": round(ms_scaled, 3)},
+        "latency_ms": {"plain": rnd(ms_plain, 3), "scaled": rnd(ms_scaled, 3)},
         "r_plus": {"plain": r1.r_plus, "scaled": r2.r_plus}, "alpha": r2.alpha_used,
         "roofline": roofline,
+        "a_streaming": streaming,
         "kernels": {kname: {"avg_us": round(v["avg_us"], 2), "launches_per_step": v["launches"] / args.steps,
                             "ms_per_step": round(v["total_ms"] / args.steps, 4)} for kname, v in kern.items()},
     }
 
     # ---------------------------------------------------------------- FP32 single-request comparison
-    if not args.no_fp32_compare and args.precision == "bf16x3":
+    if not args.no_fp32_compare and not args.no_side_timings and args.precision == "bf16x3":
         f1 = Projector(n, k, p, q, "plain", "fp32", seed=args.seed, device=dev)
         f2 = Projector(n, k, p, q, "scaled", "fp32", seed=args.seed, alpha=0.0, alpha_iters=args.alpha_iters,
                        device=dev)
@@ -244,16 +296,21 @@ def main() -> int:
         torch.cuda.synchronize()
         A_host = A.cpu().numpy().astype(np.float64)
         omega_dtype = np.float64 if args.precision == "fp64" else np.float32
-        log("oracle: plain projection on the host")
+        # the oracle pair (one plain, one scaled projection) repeated until about 10 s of host work
         t0 = time.perf_counter()
-        o1 = rnla.project(A_host, k, p, q, "plain", seed=args.seed, omega_dtype=omega_dtype)
-        log("oracle: scaled projection on the host")
-        o2 = rnla.project(A_host, k, p, q, "scaled", seed=args.seed, alpha_iters=args.alpha_iters,
-                          omega_dtype=omega_dtype)
-        cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(2.0 / cpu_s, 5), "unit": "projections/s", "cores": int(cores),
+        reps = 0
+        while True:
+            log(f"oracle: plain + scaled projection on the host (pair {reps + 1})")
+            o1 = rnla.project(A_host, k, p, q, "plain", seed=args.seed, omega_dtype=omega_dtype)
+            o2 = rnla.project(A_host, k, p, q, "scaled", seed=args.seed, alpha_iters=args.alpha_iters,
+                              omega_dtype=omega_dtype)
+            reps += 1
+            cpu_s = time.perf_counter() - t0
+            if cpu_s >= 10.0 or reps >= 4:
+                break
+        out["cpu_baseline"] = {"value": round(2.0 * reps / cpu_s, 5), "unit": "projections/s", "cores": int(cores),
                                "kind": "oracle",
-                               "sample": "one plain and one scaled projection of the same n=20000 workload "
+                               "sample": f"{reps} x (one plain + one scaled projection) of the same n={n} workload "
                                          f"(full FP64 oracle incl. Alg. 5 and the n x n rebuild), {cpu_s:.1f} s"}
         a_fro = float(np.linalg.norm(A_host))
         par = {}
@@ -276,6 +333,35 @@ def main() -> int:
     del Apos
     print(json.dumps(out), flush=True)
     return 0
+
+
+def run_counters(args, dev) -> int:
+    """The headline grouped step on a symmetric Gaussian matrix of the same size (the same kernels
+    and bytes; the generator avoids the QR that counter collection does not survive), then one
+    plain 1 GiB device-to-device copy whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    import torch
+    from paper_2410_19208_amd.torch_api import BatchProjector
+    n, k, p, q = args.n, args.k, args.p, args.q
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + 1)
+    G = torch.randn((n, n), device=dev, generator=g, dtype=torch.float32)
+    A = (G + G.T).mul_(0.5 / math.sqrt(n)).contiguous()
+    del G
+    both = BatchProjector([dict(n=n, k=k, p=p, q=q, variant="plain", precision=args.precision, seed=args.seed),
+                           dict(n=n, k=k, p=p, q=q, variant="scaled", precision=args.precision, seed=args.seed,
+                                alpha=0.0, alpha_iters=args.alpha_iters)], device=dev)
+    P1 = torch.empty_like(A)
+    P2 = torch.empty_like(A)
+    for _ in range(2):
+        both([A, A], [P1, P2])
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.add(src, 0.0, out=dst)   # one elementwise dispatch: reads 1 GiB, writes 1 GiB
+    torch.cuda.synchronize()
+    st = [r.status for r in both.results()]
+    print(json.dumps({"mode": "counters", "n": n, "status": st, "copy_bytes": 1 << 30}), flush=True)
+    return 0 if not any(st) else 1
 
 
 def run_batch(args, dev) -> int:
