@@ -492,34 +492,45 @@ void k_pass_b3(const Prob* __restrict__ probs, const int* __restrict__ tstart, i
 }
 
 // Y = sum_s part[s] in fixed order; scaled: Y = (Y + alpha Z) / alpha.  Zero outside n x r.
+// One thread per 16-byte vector of a panel column (ld is a multiple of 128, so vectors never
+// straddle columns), RD_VEC vectors per thread.
+constexpr int RD_THREADS = 256;
+constexpr int RD_VEC = 2;
 template <typename T>
-__device__ __forceinline__ void reduce_body(const Prob& p, int64_t base) {
+__device__ __forceinline__ void reduce_body(const Prob& p, int64_t vbase) {
+  constexpr int VW = 16 / sizeof(T);
+  typedef T V __attribute__((ext_vector_type(VW)));
   const int64_t P = (int64_t)p.rpad * p.ld;
-  const T* part = (const T*)p.part;
-  const T* z = (const T*)p.zm;
-  T* y = (T*)p.y;
+  const gmem<const T>* __restrict__ part = gp((const T*)p.part);
+  const gmem<const T>* __restrict__ z = gp((const T*)p.zm);
+  gmem<T>* __restrict__ y = gp((T*)p.y);
   const bool scaled = (p.variant == PSDPROJ_SCALED);
   const T alpha = (T)p.scal[S_ALPHA];
-  for (int e = threadIdx.x; e < 1024; e += 256) {
-    const int64_t idx = base + e;
+  const int split = p.split;
+#pragma unroll
+  for (int u = 0; u < RD_VEC; ++u) {
+    const int64_t idx = (vbase + (int64_t)u * RD_THREADS + threadIdx.x) * VW;
     if (idx >= P) break;
     const int col = (int)(idx / p.ld), row = (int)(idx - (int64_t)col * p.ld);
-    T v = 0;
+    V v = {};
     if (col < p.r && row < p.n) {
-      for (int s = 0; s < p.split; ++s) v += part[(int64_t)s * P + idx];
-      if (scaled) v = (v + alpha * z[idx]) / alpha;
+      for (int s = 0; s < split; ++s) v += *(const gmem<V>*)(part + (int64_t)s * P + idx);
+      if (scaled) v = (v + alpha * *(const gmem<V>*)(z + idx)) / alpha;
+#pragma unroll
+      for (int q = 0; q < VW; ++q)
+        if (row + q >= p.n) v[q] = 0;
     }
-    y[idx] = v;
+    *(gmem<V>*)(y + idx) = v;
   }
 }
 
-__global__ __launch_bounds__(256) void k_pass_reduce(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                     int nprob) {
+__global__ __launch_bounds__(RD_THREADS) void k_pass_reduce(const Prob* __restrict__ probs,
+                                                            const int* __restrict__ tstart, int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
-  const int64_t base = (int64_t)(blockIdx.x - tstart[pi]) * 1024;
-  if (p.prec == F64) reduce_body<double>(p, base);
-  else reduce_body<float>(p, base);
+  const int64_t vbase = (int64_t)(blockIdx.x - tstart[pi]) * RD_THREADS * RD_VEC;
+  if (p.prec == F64) reduce_body<double>(p, vbase);
+  else reduce_body<float>(p, vbase);
 }
 
 // ---------------------------------------------------------------- tile counts and launchers
@@ -527,7 +538,10 @@ int tiles_pass(const Prob& p) {
   const int bm = (p.prec == F64) ? PASS_BM_D : PASS_BM_F;
   return ((p.n + bm - 1) / bm) * p.split;
 }
-int tiles_reduce(const Prob& p) { return (int)(((int64_t)p.rpad * p.ld + 1023) / 1024); }
+int tiles_reduce(const Prob& p) {
+  const int64_t vecs = (int64_t)p.rpad * p.ld * (p.prec == F64 ? 8 : 4) / 16;
+  return (int)((vecs + RD_THREADS * RD_VEC - 1) / (RD_THREADS * RD_VEC));
+}
 
 #define PSD_NCB_EVEN(X) X(2) X(4) X(6) X(8) X(10) X(12) X(14) X(16)
 
@@ -570,7 +584,7 @@ void pass_init() {
 }
 
 void launch_pass_reduce(const Launch& L) {
-  hipLaunchKernelGGL(k_pass_reduce, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob);
+  hipLaunchKernelGGL(k_pass_reduce, dim3(L.grid), dim3(RD_THREADS), 0, L.stream, L.probs, L.tstart, L.nprob);
 }
 
 }  // namespace psd
