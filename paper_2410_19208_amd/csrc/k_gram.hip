@@ -49,6 +49,7 @@ __device__ void gram_tile(const Prob& p, int mode, int tile, int chunk) {
   const int r1 = min(p.ld, r0 + GRAM_CHUNK);
   const int64_t ld = p.ld;
   f64x4 acc = {0, 0, 0, 0};
+#pragma unroll 4
   for (int k = r0; k < r1; k += 16) {
     double a[4], b[4];
     load4<T>(X + (int64_t)ci * ld + k + kg * 4, a);
@@ -78,7 +79,10 @@ __global__ __launch_bounds__(256) void k_gram(const Prob* __restrict__ probs, co
 }
 
 // Sum the chunk partials (fixed order), complete the symmetric result, zero outside r x r.
+// One entry per thread (the sums over the chunks are the long part; more workgroups spread
+// them over more CUs).
 // Mode 2 symmetrises: C <- (C + C^T)/2.  A non-finite entry sets E_NONFINITE.
+constexpr int GRED_PER_BLOCK = 256;
 __global__ __launch_bounds__(256) void k_gram_reduce(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                      int nprob, int mode) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
@@ -86,9 +90,9 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const Prob* __restrict__ pr
   const int rp = p.rpad;
   const int64_t RR = (int64_t)rp * rp;
   double* dst = (mode == 2) ? p.C : p.G;
-  const int64_t base = (int64_t)(blockIdx.x - tstart[pi]) * 1024;
+  const int64_t base = (int64_t)(blockIdx.x - tstart[pi]) * GRED_PER_BLOCK;
   bool bad = false;
-  for (int e = threadIdx.x; e < 1024; e += 256) {
+  for (int e = threadIdx.x; e < GRED_PER_BLOCK; e += 256) {
     const int64_t idx = base + e;
     if (idx >= RR) break;
     const int j = (int)(idx / rp), i = (int)(idx - (int64_t)j * rp);

@@ -162,7 +162,7 @@ static int stage_tiles(const Prob& p, int kind) {
     case K_PRED: return tiles_reduce(p);
     case K_GRAM_SYM: return tiles_gram(p, false);
     case K_GRAM_FULL: return tiles_gram(p, true);
-    case K_GRED: return (int)(((int64_t)p.rpad * p.rpad + 1023) / 1024);
+    case K_GRED: return (int)(((int64_t)p.rpad * p.rpad + 255) / 256);
     case K_APPLY: case K_FACTOR: return tiles_apply(p);
     case K_BISECT: return tiles_bisect(p);
     case K_INVIT: return tiles_invit(p);
