@@ -448,7 +448,8 @@ def run_serve(args, dev) -> int:
     def snap(n):
         return min(buckets, key=lambda b: abs(math.log(b) - math.log(n)))
 
-    def run_point(qps, max_inflight, seed):
+    def run_point(qps, max_inflight, seed, precision=None):
+        precision = precision or args.precision
         count = min(args.serve_requests, max(20, int(qps * 3)))
         reqs = workloads.serving_requests(count, qps, seed)
         srv = Server(16 << 30, max_inflight, device=dev)
@@ -460,7 +461,7 @@ def run_serve(args, dev) -> int:
                 time.sleep(delay)
             nb = snap(n)
             kk = min(k, nb - p)
-            t, _ = srv.submit(pool[nb], kk, p, q, variant, args.precision, seed=len(tickets))
+            t, _ = srv.submit(pool[nb], kk, p, q, variant, precision, seed=len(tickets))
             tickets.append(t)
         lat, fin, sub, errs = [], [], [], 0
         for t in tickets:
@@ -480,13 +481,14 @@ def run_serve(args, dev) -> int:
     # warm-up: compile/initialise on a few requests
     run_point(50, 64, 99)
     points = [run_point(float(x), 64, 7000 + i) for i, x in enumerate(args.qps.split(","))]
-    base = [run_point(float(x), 1, 7000 + i) for i, x in enumerate(args.qps.split(",")[:2])]
+    # the plain FP32 form one request at a time (FIFO, nothing overlapped), same arrivals
+    base = [run_point(float(x), 1, 7000 + i, "fp32") for i, x in enumerate(args.qps.split(",")[:4])]
     out = {"metric": "PSD projection serving: throughput and p50/p99 latency at Poisson QPS",
            "value": max(pt["achieved_rps"] for pt in points), "unit": "requests/s (max achieved)", "n_gpus": 1,
            "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
            "config": {"workload": "serving: n in {256..16384} log-spaced buckets, k in {20,50,100,200}, p=10, q=1, "
                                   "plain/scaled 50/50 (alpha by Alg. 5, N=10); continuous batching, max_inflight 64"},
-           "points": points, "one_at_a_time_fifo": base}
+           "points": points, "fp32_one_at_a_time": base}
     print(json.dumps(out), flush=True)
     return 0 if all(pt["errors"] == 0 for pt in points + base) else 1
 
