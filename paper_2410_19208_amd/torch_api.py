@@ -52,7 +52,7 @@ class Projector:
 
     def __del__(self):
         plan = getattr(self, "plan", None)
-        if plan:
+        if plan and psdproj_plan_destroy is not None:   # module globals may be gone at exit
             psdproj_plan_destroy(plan)
             self.plan = None
 
@@ -133,6 +133,8 @@ class BatchProjector:
         self.result_buf = torch.zeros(len(self.plans) * ctypes.sizeof(Result), dtype=torch.uint8, device=self.device)
 
     def __del__(self):
+        if psdproj_plan_destroy is None:   # interpreter shutdown: the library goes with the process
+            return
         for p in getattr(self, "plans", []):
             psdproj_plan_destroy(p)
         self.plans = []
@@ -195,7 +197,7 @@ class Server:
         return psdproj_server_times(self.handle, ticket)
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and psdproj_server_destroy is not None:
             psdproj_server_destroy(self.handle)
             self.handle = None
             self._keep.clear()
