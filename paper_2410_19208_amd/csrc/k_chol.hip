@@ -83,41 +83,45 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
       for (int a = 0; a < 16; ++a) col[a] = dsm[a][li];   // lanes >= 16 hold copies, unused
       // right-looking Cholesky of the tile: step jj scales row jj by 1/sqrt(pivot) and updates
-      // the trailing part; pivots and row entries are broadcast with readlane (wave-uniform)
+      // the trailing part; pivots and row entries are broadcast with readlane (wave-uniform).
+      // The inverse is built in the same loop, one column per step: lane i holds row i of
+      // X = R_JJ^-1, and X[i][jj] = (delta_ij - sum_{k<jj} X[i][k] R[k][jj]) / R[jj][jj] needs
+      // only column jj of R (final by step jj) and 1/R[jj][jj], so the two dependency chains
+      // run side by side instead of one after the other.  A dropped row jj (zero row of R,
+      // unit pivot, 1/pivot taken as 0) gives a zero row and a zero column of X.
       int drops = 0;
+      double x[16];
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const double d = bcast_f64(col[jj], jj);
         const double gj = g0[16 * J + jj];
         const bool dr = !(gj > 0.0) || !(d > tol * gj) || !isfinite(d);
         const double piv = dr ? 0.0 : sqrt(d);
-        const double ip = dr ? 0.0 : 1.0 / piv;
+        // 1/piv: hardware reciprocal refined by two Newton steps (no IEEE division on the chain)
+        double ip = __builtin_amdgcn_rcp(piv);
+        ip = fma(ip, fma(-piv, ip, 1.0), ip);
+        ip = fma(ip, fma(-piv, ip, 1.0), ip);
+        ip = dr ? 0.0 : ip;
         const double rowv = (lane > jj) ? col[jj] * ip : 0.0;   // R[jj][c], c = lane
 #pragma unroll
         for (int a = jj + 1; a < 16; ++a) col[a] -= bcast_f64(rowv, a) * rowv;
         col[jj] = (lane > jj) ? rowv : (lane == jj ? (dr ? 1.0 : piv) : col[jj]);
         drops |= (dr ? 1 : 0) << jj;
+        // column jj of X; R[k][jj] (k < jj) is col[k] of lane jj
+        double acc = (lane == jj) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < jj; ++k) acc -= x[k] * bcast_f64(col[k], jj);
+        x[jj] = (lane > jj) ? 0.0 : acc * ip;
         __builtin_amdgcn_sched_barrier(0);   // keep the broadcasts of one step together
       }
-      // R_JJ^-1 (upper triangular): lane c solves R x = e_c by back substitution, with the
-      // entries R[i][k] (column k, lane k) broadcast; dropped rows of the inverse are zero
-      double x[16];
-#pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        double acc = (lane == i) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = i + 1; k < 16; ++k) acc -= bcast_f64(col[i], k) * x[k];
-        const double rii = bcast_f64(col[i], i);
-        x[i] = (i > lane || ((drops >> i) & 1)) ? 0.0 : acc / rii;
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      // R_JJ (upper, zero below) and its inverse to LDS; R_JJ back to the owner's registers
+      // R_JJ (upper, zero below; lane c holds column c) and its inverse (lane i holds row i) to
+      // LDS; R_JJ back to the owner's registers
       lds_wave_sync();
       if (lane < 16) {
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
           dsm[a][lane] = (a <= lane) ? col[a] : 0.0;
-          dinv[a][lane] = x[a];
+          dinv[lane][a] = x[a];
         }
         dflag[16 * J + lane] = (drops >> lane) & 1;
       }
