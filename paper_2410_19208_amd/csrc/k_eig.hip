@@ -97,7 +97,7 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
   if (j0 > nu && p.evals[j0] - p.evals[j0 - 1] <= gtol) return;
 
   __shared__ double U0[PSDPROJ_MAX_RANK], U1[PSDPROJ_MAX_RANK], U2[PSDPROJ_MAX_RANK];
-  __shared__ double Lm[PSDPROJ_MAX_RANK], x[PSDPROJ_MAX_RANK], b[PSDPROJ_MAX_RANK];
+  __shared__ double Lm[PSDPROJ_MAX_RANK], x[PSDPROJ_MAX_RANK], b[PSDPROJ_MAX_RANK], iu0[PSDPROJ_MAX_RANK];
   __shared__ int piv[PSDPROJ_MAX_RANK];
   const gmem<const double>* d = gp((const double*)p.td);
   const gmem<const double>* e = gp((const double*)p.te);
@@ -130,18 +130,39 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
       if (cd == 0.0) cd = tiny;
       if (lane == 0) U0[r - 1] = cd;
     }
-    for (int i = lane; i < r; i += WAVE) b[i] = start_component(jc, i);
+    __syncthreads();
+    for (int i = lane; i < r; i += WAVE) {
+      b[i] = start_component(jc, i);
+      iu0[i] = 1.0 / U0[i];   // the substitutions multiply by these
+    }
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
       // --- solve (T - lam I) x = b: forward with row swaps, then back substitution (lane 0)
+      // (the running entries stay in registers, so each step waits only on its multiply-add)
       if (lane == 0) {
+        double cur = b[0];
         for (int i = 0; i + 1 < r; ++i) {
-          if (piv[i]) { const double t = b[i]; b[i] = b[i + 1]; b[i + 1] = t; }
-          b[i + 1] -= Lm[i] * b[i];
+          double nxt = b[i + 1];
+          if (piv[i]) { const double t = cur; cur = nxt; nxt = t; }
+          nxt -= Lm[i] * cur;
+          b[i] = cur;
+          cur = nxt;
         }
-        x[r - 1] = b[r - 1] / U0[r - 1];
-        if (r >= 2) x[r - 2] = (b[r - 2] - U1[r - 2] * x[r - 1]) / U0[r - 2];
-        for (int i = r - 3; i >= 0; --i) x[i] = (b[i] - U1[i] * x[i + 1] - U2[i] * x[i + 2]) / U0[i];
+        b[r - 1] = cur;
+        double x1 = b[r - 1] * iu0[r - 1], x2 = 0.0;
+        x[r - 1] = x1;
+        if (r >= 2) {
+          const double x0 = (b[r - 2] - U1[r - 2] * x1) * iu0[r - 2];
+          x[r - 2] = x0;
+          x2 = x1;
+          x1 = x0;
+        }
+        for (int i = r - 3; i >= 0; --i) {
+          const double x0 = (b[i] - U1[i] * x1 - U2[i] * x2) * iu0[i];
+          x[i] = x0;
+          x2 = x1;
+          x1 = x0;
+        }
       }
       __syncthreads();
       // --- Gram-Schmidt against earlier members of the cluster (stored in xt)
@@ -168,26 +189,46 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
     // b holds the unit eigenvector of T; keep it for later cluster members
     gmem<double>* xs = xt + (int64_t)(jc - nu) * rp;
     for (int i = lane; i < r; i += WAVE) xs[i] = b[i];
-    // --- back-transform u = H_0 H_1 ... H_{r-3} b
+    // --- back-transform u = H_0 H_1 ... H_{r-3} b, in registers: lane l holds entries
+    // l + 64 q (q < 4); the next reflector's column is loaded while the current one is applied
+    double bv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bv[q] = (lane + 64 * q < r) ? b[lane + 64 * q] : 0.0;
+    const gmem<const double>* Hc = gp((const double*)p.H);
+    auto hload = [&](int jh, double (&h)[4]) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = Hc[(int64_t)jh * rp + min(lane + 64 * q, rp - 1)];
+    };
+    double hc[4], hn[4];
+    if (r >= 3) hload(r - 3, hc);
     for (int jh = r - 3; jh >= 0; --jh) {
+      if (jh > 0) hload(jh - 1, hn);
       const double tau = p.tau[jh];
-      if (tau == 0.0) continue;
-      const gmem<const double>* col = gp((const double*)p.H) + (int64_t)jh * rp;
-      double s = 0.0;
-      for (int i = jh + 1 + lane; i < r; i += WAVE) s += ((i == jh + 1) ? 1.0 : col[i]) * b[i];
-      s = wave_sum(s) * tau;
-      __syncthreads();
-      for (int i = jh + 1 + lane; i < r; i += WAVE) b[i] -= s * ((i == jh + 1) ? 1.0 : col[i]);
-      __syncthreads();
+      double v[4], s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        v[q] = (i == jh + 1) ? 1.0 : ((i > jh + 1 && i < r) ? hc[q] : 0.0);
+        s += v[q] * bv[q];
+      }
+      s = wave_allsum(s) * tau;   // tau = 0: identity reflector
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] -= s * v[q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hc[q] = hn[q];
     }
     // --- store: column c = r-1-jc (descending eigenvalue order)
     const int c = r - 1 - jc;
     const double wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
     const double sw = (wgt > 0.0 && isfinite(wgt)) ? sqrt(wgt) : 0.0;
-    for (int i = lane; i < rp; i += WAVE) {
-      const double u = (i < r) ? b[i] : 0.0;
-      p.V[(int64_t)c * rp + i] = u;
-      p.F[(int64_t)i * rp + c] = u * sw;   // row-major (read by the factor apply)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      if (i < rp) {
+        const double u = (i < r) ? bv[q] : 0.0;
+        p.V[(int64_t)c * rp + i] = u;
+        p.F[(int64_t)i * rp + c] = u * sw;   // row-major (read by the factor apply)
+      }
     }
     __syncthreads();
     ++jc;
