@@ -18,7 +18,32 @@ namespace psd {
 
 
 
-// One wave per eigenvalue index j (ascending); lane l tests x_l = lo + (hi - lo)(l+1)/65.
+// Sturm counts (eigenvalues of T below x) at two points at once: two independent recurrences
+// interleaved, and 1/q as a hardware reciprocal refined by two Newton steps instead of an
+// IEEE division, so the dependent chain per step is a few fused multiply-adds.
+__device__ __forceinline__ void sturm_count2(const double* d, const double* e2, int r, double x0, double x1,
+                                             double pivmin, int& c0, int& c1) {
+  double q0 = d[0] - x0, q1 = d[0] - x1;
+  c0 = q0 < 0.0;
+  c1 = q1 < 0.0;
+  for (int i = 1; i < r; ++i) {
+    if (fabs(q0) < pivmin) q0 = -pivmin;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    double r0 = __builtin_amdgcn_rcp(q0), r1 = __builtin_amdgcn_rcp(q1);
+    r0 = fma(r0, fma(-q0, r0, 1.0), r0);
+    r1 = fma(r1, fma(-q1, r1, 1.0), r1);
+    r0 = fma(r0, fma(-q0, r0, 1.0), r0);
+    r1 = fma(r1, fma(-q1, r1, 1.0), r1);
+    const double di = d[i], ei = e2[i - 1];
+    q0 = (di - x0) - ei * r0;
+    q1 = (di - x1) - ei * r1;
+    c0 += q0 < 0.0;
+    c1 += q1 < 0.0;
+  }
+}
+
+// One wave per eigenvalue index j (ascending); lane l tests x = lo + (hi - lo)(m+1)/129 at
+// m = l and m = l + 64 (128-way multisection).
 __global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                 int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
@@ -35,21 +60,34 @@ __global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, 
     if (lane == 0) p.evals[j] = __builtin_nan("");
     return;
   }
+  __shared__ double dl[4][PSDPROJ_MAX_RANK], el[4][PSDPROJ_MAX_RANK];   // per wave: T's d and e^2
+  const int w = wave_id();
+  for (int i = lane; i < r; i += WAVE) {
+    dl[w][i] = d[i];
+    el[w][i] = (i + 1 < r) ? e2[i] : 0.0;
+  }
+  lds_wave_sync();
   for (int round = 0; round < 24; ++round) {
     const double width = hi - lo;
     const double tol = 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin;
     if (!(width > 2.0 * tol)) break;
-    const double x = lo + width * (double)(lane + 1) / 65.0;
-    const int c = sturm_count(d, e2, r, x, pivmin);
-    // first lane whose count exceeds j bounds the eigenvalue from above
-    const unsigned long long mask = __ballot(c > j);
+    const double x0 = lo + width * (double)(lane + 1) / 129.0;
+    const double x1 = lo + width * (double)(lane + 65) / 129.0;
+    int c0, c1;
+    sturm_count2(dl[w], el[w], r, x0, x1, pivmin, c0, c1);
+    // the first point (in increasing order) whose count exceeds j bounds the eigenvalue above
+    const unsigned long long m0 = __ballot(c0 > j), m1 = __ballot(c1 > j);
     double nlo = lo, nhi = hi;
-    if (mask) {
-      const int f = __ffsll((long long)mask) - 1;
-      nhi = __shfl(x, f, 64);
-      if (f > 0) nlo = __shfl(x, f - 1, 64);
+    if (m0) {
+      const int f = __ffsll((long long)m0) - 1;
+      nhi = __shfl(x0, f, 64);
+      if (f > 0) nlo = __shfl(x0, f - 1, 64);
+    } else if (m1) {
+      const int f = __ffsll((long long)m1) - 1;
+      nhi = __shfl(x1, f, 64);
+      nlo = (f > 0) ? __shfl(x1, f - 1, 64) : __shfl(x0, 63, 64);
     } else {
-      nlo = __shfl(x, 63, 64);
+      nlo = __shfl(x1, 63, 64);
     }
     lo = nlo;
     hi = nhi;
@@ -99,30 +137,39 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
   __shared__ double U0[PSDPROJ_MAX_RANK], U1[PSDPROJ_MAX_RANK], U2[PSDPROJ_MAX_RANK];
   __shared__ double Lm[PSDPROJ_MAX_RANK], x[PSDPROJ_MAX_RANK], b[PSDPROJ_MAX_RANK], iu0[PSDPROJ_MAX_RANK];
   __shared__ int piv[PSDPROJ_MAX_RANK];
+  __shared__ double dl[PSDPROJ_MAX_RANK], el[PSDPROJ_MAX_RANK];
   const gmem<const double>* d = gp((const double*)p.td);
   const gmem<const double>* e = gp((const double*)p.te);
   gmem<double>* xt = gp(p.xt);
   const double tiny = 2.220446049250313e-16 * fmax(tnorm, 1e-300);
 
+  // T's diagonal and off-diagonal into LDS once: the LU recurrence below then waits on LDS
+  // reads rather than on global loads at every step
+  for (int i = lane; i < r; i += WAVE) {
+    dl[i] = d[i];
+    el[i] = (i + 1 < r) ? e[i] : 0.0;
+  }
+  __syncthreads();
   int jc = j0;
   do {
     const double lam = p.evals[jc];
-    // --- LU of T - lam I with partial pivoting (all lanes compute the same values)
+    // --- LU of T - lam I with partial pivoting (all lanes compute the same values and store
+    // the same entries)
     {
-      double cd = d[0] - lam, cs = (r > 1) ? e[0] : 0.0;
+      double cd = dl[0] - lam, cs = (r > 1) ? el[0] : 0.0;
       for (int i = 0; i + 1 < r; ++i) {
-        const double nd = d[i + 1] - lam;
-        const double ns = (i + 2 < r) ? e[i + 1] : 0.0;
-        const double sb = e[i];
+        const double nd = dl[i + 1] - lam;
+        const double ns = (i + 2 < r) ? el[i + 1] : 0.0;
+        const double sb = el[i];
         if (fabs(cd) >= fabs(sb)) {
           if (cd == 0.0) cd = tiny;
           const double m = sb / cd;
-          if (lane == 0) { U0[i] = cd; U1[i] = cs; U2[i] = 0.0; Lm[i] = m; piv[i] = 0; }
+          U0[i] = cd; U1[i] = cs; U2[i] = 0.0; Lm[i] = m; piv[i] = 0;
           cd = nd - m * cs;
           cs = ns;
         } else {
           const double m = cd / sb;
-          if (lane == 0) { U0[i] = sb; U1[i] = nd; U2[i] = ns; Lm[i] = m; piv[i] = 1; }
+          U0[i] = sb; U1[i] = nd; U2[i] = ns; Lm[i] = m; piv[i] = 1;
           cd = cs - m * nd;
           cs = -m * ns;
         }
