@@ -3,17 +3,19 @@
 //
 // The upper-triangle 16x16 tiles of the symmetric r_pad x r_pad matrix live in registers.  A
 // wave owns whole column blocks, paired as J and nb-1-J so every wave holds nb+1 tiles; lane l
-// of a tile holds row l/4, columns 4*(l%4) .. +3.  Step j (j = 0 .. r-3):
-//   1. the owners of row j publish it through LDS (double-buffered);
-//   2. every wave forms the reflector H_j = I - tau v v^T that maps C[j+1:, j] to beta e_1
-//      (redundantly, identical arithmetic in every wave, so no extra barrier);
-//   3. p = tau C2 v (C2 = trailing block): per tile, the row sums C_IJ v_J (a quad reduction
-//      with DPP moves) go to LDS; the column sums C_IJ^T v_I accumulate in registers over a
-//      column block and are reduced once per block (16-lane reduce-scatter); p_i adds the nb
-//      row-block terms and the column-block term in a fixed order; K = tau/2 p^T v,
-//      w = p - K v;
-//   4. C2 -= v w^T + w v^T on the registers.
-// Tiles left of or above the trailing block are skipped (wave-uniform tests).
+// of a tile holds row l/4, columns 4*(l%4) .. +3.  Step j (j = 0 .. r-3), three barriers:
+//   1. row j is in LDS (published by its owners at the end of the previous step, with the
+//      per-wave sums of squares of its entries past the subdiagonal); every wave forms the
+//      reflector H_j = I - tau v v^T mapping C[j+1:, j] to beta e_1 with identical arithmetic,
+//      and a private LDS copy of v;
+//   2. products with the trailing block C2: per tile the row sums C_IJ v_J (quad reduction)
+//      go to LDS, the column sums C_IJ^T v_I accumulate over a column block and are reduced
+//      once per block, and each wave adds its part of v^T C2 v;
+//   3. one thread per row: p_i = tau (C2 v)_i from the row-block and column-block terms in a
+//      fixed order, K = tau/2 p^T v = tau^2/2 v^T C2 v, w = p - K v, shared through LDS;
+//   4. C2 -= v w^T + w v^T on the registers; the owners of row j+1 publish it.
+// v and w vanish outside C2, so the products and the update need no masks; tiles left of or
+// above C2 are skipped (wave-uniform tests).
 // Outputs: diagonal d and off-diagonal e of T, tau_j, the reflector vectors v (entries j+2..r-1)
 // in column j of H, the Gershgorin interval, and the Sturm count nu of eigenvalues below the
 // clamp threshold (0 for Alg. 2, 1 for Alg. 3): only the r - nu eigenpairs above it are kept.
@@ -61,10 +63,16 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
   gmem<double>* __restrict__ tem = gp(p.te);
   gmem<double>* __restrict__ taum = gp(p.tau);
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, lr = lane >> 2, lc = lane & 3;
-  __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];
-  __shared__ double rpart[TD_NB][TD_NB][16];   // [I][J][row]: C_IJ v_J
-  __shared__ double cpart[TD_NB][16];          // [J][col]: sum over I < J of C_IJ^T v_I
-  __shared__ double pvec[PSDPROJ_MAX_RANK];
+  __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];        // row j of the reduced matrix (double-buffered)
+  __shared__ double sqp[2][TD_WAVES];                   // per-wave parts of ||row j, columns >= j+2||^2
+  __shared__ double rpart[TD_NB][16][TD_NB];            // [I][row][J]: C_IJ v_J (zero where J < I)
+  __shared__ double cpart[TD_NB][16];                   // [J][col]: sum over I < J of C_IJ^T v_I
+  __shared__ double kpart[TD_WAVES];                    // per-wave parts of v^T C2 v
+  __shared__ double vv[PSDPROJ_MAX_RANK], wv[PSDPROJ_MAX_RANK];
+  __shared__ double vpw[TD_WAVES][PSDPROJ_MAX_RANK];    // per-wave copy of v (no barrier needed)
+  double* __restrict__ vp = vpw[wave];
+
+  for (int e = tid; e < TD_NB * 16 * TD_NB; e += TD_THREADS) (&rpart[0][0][0])[e] = 0.0;
 
   // column blocks of this wave: bA = wave, bB = nb-1-wave (bB used only when bB > bA)
   const int bA = wave, bB = nb - 1 - wave;
@@ -90,25 +98,43 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     }
   }
 
-  for (int j = 0; j + 2 < r; ++j) {
-    double* buf = rowbuf[j & 1];
-    const int jb = j >> 4, ji = j & 15;
-    // 1. publish row j: slot I = jb of every column block J >= jb (entries left of j unused)
+  // Row jn of the registers -> rowbuf[jn & 1]; the squares of its entries in columns >= jn+2
+  // summed per wave -> sqp[jn & 1][wave] (zero from waves holding none of the row).
+  auto publish_part = [&](int s, int jn, double& sq) {
+    int I, J;
+    slot_ij(s, I, J);
+    if (I == (jn >> 4) && lr == (jn & 15)) {
+      const int b0 = 16 * J + 4 * lc;
+      double* dst = rowbuf[jn & 1] + b0;
+      *(double2*)dst = double2{reg[s][0], reg[s][1]};
+      *(double2*)(dst + 2) = double2{reg[s][2], reg[s][3]};
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      int I, J;
-      slot_ij(s, I, J);
-      if (slot_ok(s) && I == jb && lr == ji) {
-        double* dst = buf + 16 * J + 4 * lc;
-        *(double2*)dst = double2{reg[s][0], reg[s][1]};
-        *(double2*)(dst + 2) = double2{reg[s][2], reg[s][3]};
-      }
+      for (int q = 0; q < 4; ++q)
+        if (b0 + q >= jn + 2) sq = fma(reg[s][q], reg[s][q], sq);
     }
+  };
+  auto publish_sq = [&](int jn, double sq) {
+    sq += dpp_f64<DPP_XOR1>(sq);
+    sq += dpp_f64<DPP_XOR2>(sq);
+    if (lane == 4 * (jn & 15)) sqp[jn & 1][wave] = sq;
+  };
+  {
+    double sq = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (slot_ok(s)) publish_part(s, 0, sq);
+    publish_sq(0, sq);
+  }
+
+  for (int j = 0; j + 2 < r; ++j) {
     lds_barrier();
-    // 2. reflector: x = buf[j+1 ..], sigma = ||x[1:]||^2 (wave reduction, same in every wave)
-    double part = 0.0;
-    for (int i = j + 2 + lane; i < r; i += WAVE) part += buf[i] * buf[i];
-    const double sigma = wave_allsum(part);
+    const double* __restrict__ buf = rowbuf[j & 1];
+    const int jb = j >> 4;
+    // 1. reflector H_j = I - tau v v^T mapping C[j+1:, j] to beta e_1 (same arithmetic in
+    //    every wave): alpha = C[j+1][j], sigma = ||C[j+2:, j]||^2
+    double sigma = 0.0;
+#pragma unroll
+    for (int w = 0; w < TD_WAVES; ++w) sigma += sqp[j & 1][w];
     const double alpha = buf[j + 1];
     double tau = 0.0, beta = alpha, sc = 0.0;
     if (sigma > 0.0) {
@@ -117,105 +143,122 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
       tau = (beta - alpha) / beta;
       sc = 1.0 / (alpha - beta);
     }
-    if (tid == 0) {
-      tdm[j] = buf[j];
-      tem[j] = beta;
-      taum[j] = tau;
-    }
-    for (int i = j + 2 + tid; i < r; i += TD_THREADS) Hm[(int64_t)j * rp + i] = buf[i] * sc;
-    if (tau == 0.0) continue;   // uniform: every wave computed the same tau
-    // v_i: 0 (i <= j), 1 (i = j+1), buf[i] * sc (i >= j+2); padding (>= r) is zero in buf
+    // v_i: 0 (i <= j), 1 (i = j+1), C[i][j] * sc (i >= j+2); zero in the padding (>= r).
+    // With tau = 0 the step below leaves the registers unchanged (w = 0).
     auto vval = [&](int i, double x) { return (i > j + 1) ? x * sc : (i == j + 1 ? 1.0 : 0.0); };
+    {
+      const int i0 = 4 * lane;
+      if (i0 < rp) {
+        const double2 x01 = *(const double2*)(buf + i0);
+        const double2 x23 = *(const double2*)(buf + i0 + 2);
+        *(double2*)(vp + i0) = double2{vval(i0, x01.x), vval(i0 + 1, x01.y)};
+        *(double2*)(vp + i0 + 2) = double2{vval(i0 + 2, x23.x), vval(i0 + 3, x23.y)};
+      }
+    }
+    lds_wave_sync();
 
-    // 3a. row sums per tile -> rpart; column sums per column block -> cpart
+    // 2. products with the trailing block C2 (v vanishes outside it, so no masking): per tile
+    //    the row sums C_IJ v_J (quad reduction) -> rpart; the column sums C_IJ^T v_I over a
+    //    column block -> cpart; v^T C2 v from the lane partials -> kpart.
+    double kv = 0.0;
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
       const int J = blk ? bB : bA;
       const bool have = blk ? hasB : hasA;
-      if (!have || 16 * J + 15 <= j) continue;   // uniform: no trailing columns in this block
+      if (!have || J < jb) continue;   // uniform: no trailing columns in this block
       const int b0 = 16 * J + 4 * lc;
-      const double2 x01 = *(const double2*)(buf + b0);
-      const double2 x23 = *(const double2*)(buf + b0 + 2);
-      const double vb[4] = {vval(b0, x01.x), vval(b0 + 1, x01.y), vval(b0 + 2, x23.x), vval(b0 + 3, x23.y)};
+      const double2 v01 = *(const double2*)(vp + b0);
+      const double2 v23 = *(const double2*)(vp + b0 + 2);
+      const double vb[4] = {v01.x, v01.y, v23.x, v23.y};
       double cs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         int I, JJ;
         slot_ij(s, I, JJ);
         if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;   // compile-time slot, uniform block
-        if (16 * I + 15 <= j) continue;                          // uniform: rows all above the block
-        const int a = 16 * I + lr;
-        const double va = vval(a, buf[a]);
-        const bool ra = a > j;
-        double rs = 0.0;
+        if (I < jb) continue;                                    // uniform: rows all above the block
+        const double va = vp[16 * I + lr];
+        double rs = reg[s][0] * vb[0];
+        rs = fma(reg[s][1], vb[1], rs);
+        rs = fma(reg[s][2], vb[2], rs);
+        rs = fma(reg[s][3], vb[3], rs);
+        kv = fma(va, rs, kv);
+        if (I != J) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double x = (ra && b0 + q > j) ? reg[s][q] : 0.0;
-          rs += x * vb[q];
-          if (I != J) cs[q] += x * va;
+          for (int q = 0; q < 4; ++q) cs[q] = fma(reg[s][q], va, cs[q]);
         }
         rs += dpp_f64<DPP_XOR1>(rs);
         rs += dpp_f64<DPP_XOR2>(rs);
-        if (lc == 0) rpart[I][J][lr] = rs;
+        if (lc == 0) rpart[I][lr][J] = rs;
       }
+      // the tiles above the diagonal count twice in v^T C2 v: once more through the column sums
+#pragma unroll
+      for (int q = 0; q < 4; ++q) kv = fma(cs[q], vb[q], kv);
       colsum16(cs, lane);
       if ((lane & 12) == 0) cpart[J][4 * lc + ((lane >> 4) & 3)] = cs[0];
     }
+    kv = wave_allsum(kv);
+    if (lane == 0) kpart[wave] = kv;
     lds_barrier();
-    // 3b. p_i = tau * (sum_{J >= i/16} C_{i/16,J} v_J + sum_{I < i/16} C_{I,i/16}^T v_I)
-    for (int i = tid; i < rp; i += TD_THREADS) {
+
+    // 3. p = tau C2 v, K = tau/2 p^T v = tau^2/2 v^T C2 v, w = p - K v -> vv, wv (shared);
+    //    v_j (entries j+2 ..) into column j of H, and d_j, e_j, tau_j.
+    if (tid < rp) {
+      const int i = tid, ib = i >> 4, ii = i & 15;
       double s = 0.0;
-      if (i > j && i < r) {
-        const int ib = i >> 4, ii = i & 15;
 #pragma unroll
-        for (int J = 0; J < TD_NB; ++J) {
-          const double t = rpart[ib][J][ii];   // in bounds for every J; stale entries are not added
-          s += (J >= ib && J < nb) ? t : 0.0;
-        }
-        s += cpart[ib][ii];
-        s *= tau;
+      for (int J = 0; J < TD_NB; J += 2) {
+        const double2 t = *(const double2*)&rpart[ib][ii][J];
+        s += t.x;
+        s += t.y;
       }
-      pvec[i] = s;   // zero outside the trailing block and in the padding
+      s += cpart[ib][ii];
+      double vcv = 0.0;
+#pragma unroll
+      for (int w = 0; w < TD_WAVES; ++w) vcv += kpart[w];
+      const double K = 0.5 * tau * tau * vcv;
+      const double vi = vval(i, buf[i]);
+      const double pi_ = (i > j && i < r) ? tau * s : 0.0;
+      vv[i] = vi;
+      wv[i] = pi_ - K * vi;
+      if (i >= j + 2 && i < r) Hm[(int64_t)j * rp + i] = vi;
+      if (i == 0) {
+        tdm[j] = buf[j];
+        tem[j] = beta;
+        taum[j] = tau;
+      }
     }
     lds_barrier();
-    // K = tau/2 p^T v (wave reduction, same in every wave)
-    double dp = 0.0;
-    for (int i = j + 1 + lane; i < r; i += WAVE) dp += pvec[i] * vval(i, buf[i]);
-    const double K = 0.5 * tau * wave_allsum(dp);
-    // 4. C2 -= v w^T + w v^T, w = p - K v (zero outside the trailing block)
+
+    // 4. C2 -= v w^T + w v^T on the registers (v, w vanish outside C2), and row j+1 published
+    //    for the next step.
+    double sq = 0.0;
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
       const int J = blk ? bB : bA;
       const bool have = blk ? hasB : hasA;
-      if (!have || 16 * J + 15 <= j) continue;
+      if (!have || J < jb) continue;
       const int b0 = 16 * J + 4 * lc;
-      const double2 x01 = *(const double2*)(buf + b0);
-      const double2 x23 = *(const double2*)(buf + b0 + 2);
-      const double2 p01 = *(const double2*)(pvec + b0);
-      const double2 p23 = *(const double2*)(pvec + b0 + 2);
-      const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
-      const double pb[4] = {p01.x, p01.y, p23.x, p23.y};
-      double vb[4], wb[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        vb[q] = vval(b0 + q, xb[q]);
-        wb[q] = pb[q] - K * vb[q];   // pvec is zero for b <= j
-      }
+      const double2 v01 = *(const double2*)(vv + b0);
+      const double2 v23 = *(const double2*)(vv + b0 + 2);
+      const double2 w01 = *(const double2*)(wv + b0);
+      const double2 w23 = *(const double2*)(wv + b0 + 2);
+      const double vb[4] = {v01.x, v01.y, v23.x, v23.y};
+      const double wb[4] = {w01.x, w01.y, w23.x, w23.y};
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         int I, JJ;
         slot_ij(s, I, JJ);
         if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;
-        if (16 * I + 15 <= j) continue;
+        if (I < jb) continue;
         const int a = 16 * I + lr;
-        const double va = vval(a, buf[a]);
-        const double wa = pvec[a] - K * va;
+        const double va = vv[a], wa = wv[a];
 #pragma unroll
         for (int q = 0; q < 4; ++q) reg[s][q] -= va * wb[q] + wa * vb[q];
+        publish_part(s, j + 1, sq);
       }
     }
-    // rows >= j+1 of the registers are consistent for the next step; rpart/cpart/pvec are
-    // rewritten only after the next step's first barrier.
+    publish_sq(j + 1, sq);
   }
   // last 2x2 (or 1x1) block
   if (r >= 2) {
