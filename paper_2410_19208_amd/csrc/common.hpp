@@ -133,6 +133,14 @@ __device__ __forceinline__ void lds_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton steps (x finite, nonzero,
+// normal); within an ulp or two of the IEEE quotient, with a short dependent chain.
+__device__ __forceinline__ double rcp_f64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+
 // Value of v in lane `src` (a constant or wave-uniform index), as a wave-uniform double.
 __device__ __forceinline__ double bcast_f64(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -146,6 +154,14 @@ template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// The same for patterns where every lane has a valid source lane (quad permutations, row
+// rotations): no old value to preserve, so no register initialisation before the moves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1,0,3,2]

@@ -47,8 +47,8 @@ __device__ __forceinline__ void colsum16(double (&c)[4], int lane) {
     const double keep = up ? c[1] : c[0], send = up ? c[0] : c[1];
     c[0] = keep + __shfl_xor(send, 16, 64);
   }
-  c[0] += dpp_f64<DPP_ROR4>(c[0]);
-  c[0] += dpp_f64<DPP_ROR8>(c[0]);
+  c[0] += dpp_perm_f64<DPP_ROR4>(c[0]);
+  c[0] += dpp_perm_f64<DPP_ROR8>(c[0]);
 }
 
 template <int NS>   // register slots per wave: nb + 1 (15: r_pad <= 224, 17: r_pad = 256)
@@ -65,26 +65,30 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, lr = lane >> 2, lc = lane & 3;
   __shared__ double rowbuf[2][PSDPROJ_MAX_RANK];        // row j of the reduced matrix (double-buffered)
   __shared__ double sqp[2][TD_WAVES];                   // per-wave parts of ||row j, columns >= j+2||^2
-  __shared__ double rpart[TD_NB][16][TD_NB];            // [I][row][J]: C_IJ v_J (zero where J < I)
+  __shared__ double rpart[TD_NB][TD_NB / 2][16][2];     // [I][J/2][row][J%2]: C_IJ v_J (zero where J < I)
   __shared__ double cpart[TD_NB][16];                   // [J][col]: sum over I < J of C_IJ^T v_I
   __shared__ double kpart[TD_WAVES];                    // per-wave parts of v^T C2 v
-  __shared__ double vv[PSDPROJ_MAX_RANK], wv[PSDPROJ_MAX_RANK];
+  __shared__ double2 vw[PSDPROJ_MAX_RANK];              // (v_i, w_i)
   __shared__ double vpw[TD_WAVES][PSDPROJ_MAX_RANK];    // per-wave copy of v (no barrier needed)
   double* __restrict__ vp = vpw[wave];
 
-  for (int e = tid; e < TD_NB * 16 * TD_NB; e += TD_THREADS) (&rpart[0][0][0])[e] = 0.0;
+  for (int e = tid; e < TD_NB * 16 * TD_NB; e += TD_THREADS) (&rpart[0][0][0][0])[e] = 0.0;
 
-  // column blocks of this wave: bA = wave, bB = nb-1-wave (bB used only when bB > bA)
-  const int bA = wave, bB = nb - 1 - wave;
-  const bool hasA = bA <= bB;
-  const bool hasB = bA < bB;
+  // column blocks of this wave: bA = wave, bB = nb-1-wave (bB used only when bB > bA).  bA is
+  // re-read through an empty asm at the start of each phase so that the per-slot conditions
+  // derived from it are scalar compares made where they are used, not lane masks kept live
+  // across the whole loop.
+  int bA = wave;
+  auto refresh = [&] { __asm__ volatile("" : "+s"(bA)); };
+  auto blkJ = [&](int blk) { return blk ? nb - 1 - bA : bA; };
+  auto blk_has = [&](int blk) { return blk ? bA < nb - 1 - bA : bA <= nb - 1 - bA; };
   // slot s: s <= bA -> tile (s, bA); else tile (s - bA - 1, bB)
   auto slot_ij = [&](int s, int& I, int& J) {
     if (s <= bA) { I = s; J = bA; }
-    else { I = s - bA - 1; J = bB; }
+    else { I = s - bA - 1; J = nb - 1 - bA; }
   };
-  auto slot_ok = [&](int s) { return s <= bA ? hasA : (hasB && s - bA - 1 <= bB); };
-
+  auto slot_ok = [&](int s) { return s <= bA ? blk_has(0) : (blk_has(1) && s - bA - 1 <= nb - 1 - bA); };
+  constexpr int SA_END = NS < 8 ? NS : 8;   // bA <= (nb - 1) / 2 <= 7 whenever block A exists
   double reg[NS][4];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -103,7 +107,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
   auto publish_part = [&](int s, int jn, double& sq) {
     int I, J;
     slot_ij(s, I, J);
-    if (I == (jn >> 4) && lr == (jn & 15)) {
+    if (I == (jn >> 4) && lr == (jn & 15)) {   // scalar test first, then the lane test
       const int b0 = 16 * J + 4 * lc;
       double* dst = rowbuf[jn & 1] + b0;
       *(double2*)dst = double2{reg[s][0], reg[s][1]};
@@ -114,8 +118,8 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     }
   };
   auto publish_sq = [&](int jn, double sq) {
-    sq += dpp_f64<DPP_XOR1>(sq);
-    sq += dpp_f64<DPP_XOR2>(sq);
+    sq += dpp_perm_f64<DPP_XOR1>(sq);
+    sq += dpp_perm_f64<DPP_XOR2>(sq);
     if (lane == 4 * (jn & 15)) sqp[jn & 1][wave] = sq;
   };
   {
@@ -129,20 +133,37 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
   for (int j = 0; j + 2 < r; ++j) {
     lds_barrier();
     const double* __restrict__ buf = rowbuf[j & 1];
-    const int jb = j >> 4;
+    // block index of column j in a scalar register, so that the per-slot tests below are
+    // scalar compares and branches
+    const int jb = __builtin_amdgcn_readfirstlane(j) >> 4;
     // 1. reflector H_j = I - tau v v^T mapping C[j+1:, j] to beta e_1 (same arithmetic in
-    //    every wave): alpha = C[j+1][j], sigma = ||C[j+2:, j]||^2
+    //    every wave): alpha = C[j+1][j], sigma = ||C[j+2:, j]||^2; tau = 0 when sigma = 0.
+    //    sqrt and the two reciprocals are hardware estimates refined by Goldschmidt / Newton
+    //    steps (no IEEE division on the chain).
     double sigma = 0.0;
 #pragma unroll
     for (int w = 0; w < TD_WAVES; ++w) sigma += sqp[j & 1][w];
     const double alpha = buf[j + 1];
-    double tau = 0.0, beta = alpha, sc = 0.0;
-    if (sigma > 0.0) {
-      const double mu = sqrt(alpha * alpha + sigma);
-      beta = (alpha <= 0.0) ? mu : -mu;
-      tau = (beta - alpha) / beta;
-      sc = 1.0 / (alpha - beta);
+    const double x2 = fma(alpha, alpha, sigma);
+    const double y0 = __builtin_amdgcn_rsq(x2);
+    double g = x2 * y0, h = 0.5 * y0;
+    const double e0 = fma(-h, g, 0.5);
+    g = fma(g, e0, g);
+    h = fma(h, e0, h);
+    g = fma(fma(-g, g, x2), h, g);
+    g = fma(fma(-g, g, x2), h, g);   // g = sqrt(alpha^2 + sigma)
+    double bt = (alpha <= 0.0) ? g : -g;
+    double rb = rcp_f64(bt), ra = rcp_f64(alpha - bt);
+    if (!(x2 > 1e-280 && x2 < 1e280)) {   // far from 1: IEEE sqrt and division (same in all lanes)
+      const double mu = sqrt(x2);
+      bt = (alpha <= 0.0) ? mu : -mu;
+      rb = 1.0 / bt;
+      ra = 1.0 / (alpha - bt);
     }
+    const bool refl = sigma > 0.0;
+    const double beta = refl ? bt : alpha;
+    const double tau = refl ? (bt - alpha) * rb : 0.0;
+    const double sc = refl ? ra : 0.0;
     // v_i: 0 (i <= j), 1 (i = j+1), C[i][j] * sc (i >= j+2); zero in the padding (>= r).
     // With tau = 0 the step below leaves the registers unchanged (w = 0).
     auto vval = [&](int i, double x) { return (i > j + 1) ? x * sc : (i == j + 1 ? 1.0 : 0.0); };
@@ -161,35 +182,42 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     //    the row sums C_IJ v_J (quad reduction) -> rpart; the column sums C_IJ^T v_I over a
     //    column block -> cpart; v^T C2 v from the lane partials -> kpart.
     double kv = 0.0;
+    refresh();
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      const int J = blk ? bB : bA;
-      const bool have = blk ? hasB : hasA;
+      const int J = blkJ(blk);
+      const bool have = blk_has(blk);
       if (!have || J < jb) continue;   // uniform: no trailing columns in this block
       const int b0 = 16 * J + 4 * lc;
       const double2 v01 = *(const double2*)(vp + b0);
       const double2 v23 = *(const double2*)(vp + b0 + 2);
       const double vb[4] = {v01.x, v01.y, v23.x, v23.y};
       double cs[4] = {0.0, 0.0, 0.0, 0.0};
+      // The block's slots hold row blocks 0 .. J in slot order; they are taken from I = J down
+      // to I = jb, and v at the next slot's rows is loaded one slot ahead into the other of two
+      // registers chosen by slot parity (both start with the first slot's value), so that no
+      // copies are needed where the skipped slots above the block join the chain.
+      const int slo = blk ? bA + 1 : 0, shi = slo + J;   // slots of this block
+      double vx[2];
+      vx[0] = vx[1] = vp[16 * J + lr];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        int I, JJ;
-        slot_ij(s, I, JJ);
-        if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;   // compile-time slot, uniform block
-        if (I < jb) continue;                                    // uniform: rows all above the block
-        const double va = vp[16 * I + lr];
+      for (int s = (blk ? NS : SA_END) - 1; s >= blk; --s) {   // block A slots: s <= bA <= 7
+        if (s > shi) continue;              // above the block (before the chain starts)
+        const int I = s - slo;
+        if (s < slo || I < jb) break;       // end of the block or of the trailing rows
+        const double va = vx[s & 1];
+        vx[(s + 1) & 1] = vp[16 * max(I - 1, 0) + lr];
         double rs = reg[s][0] * vb[0];
         rs = fma(reg[s][1], vb[1], rs);
         rs = fma(reg[s][2], vb[2], rs);
         rs = fma(reg[s][3], vb[3], rs);
         kv = fma(va, rs, kv);
-        if (I != J) {
+        const double vc = (I != J) ? va : 0.0;   // the diagonal tile has no mirrored part
 #pragma unroll
-          for (int q = 0; q < 4; ++q) cs[q] = fma(reg[s][q], va, cs[q]);
-        }
-        rs += dpp_f64<DPP_XOR1>(rs);
-        rs += dpp_f64<DPP_XOR2>(rs);
-        if (lc == 0) rpart[I][lr][J] = rs;
+        for (int q = 0; q < 4; ++q) cs[q] = fma(reg[s][q], vc, cs[q]);
+        rs += dpp_perm_f64<DPP_XOR1>(rs);
+        rs += dpp_perm_f64<DPP_XOR2>(rs);
+        rpart[I][J >> 1][lr][J & 1] = rs;   // the four lanes of the quad store the same sum
       }
       // the tiles above the diagonal count twice in v^T C2 v: once more through the column sums
 #pragma unroll
@@ -208,7 +236,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
       double s = 0.0;
 #pragma unroll
       for (int J = 0; J < TD_NB; J += 2) {
-        const double2 t = *(const double2*)&rpart[ib][ii][J];
+        const double2 t = *(const double2*)&rpart[ib][J >> 1][ii][0];   // consecutive rows: no bank conflicts
         s += t.x;
         s += t.y;
       }
@@ -219,8 +247,7 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
       const double K = 0.5 * tau * tau * vcv;
       const double vi = vval(i, buf[i]);
       const double pi_ = (i > j && i < r) ? tau * s : 0.0;
-      vv[i] = vi;
-      wv[i] = pi_ - K * vi;
+      vw[i] = double2{vi, pi_ - K * vi};
       if (i >= j + 2 && i < r) Hm[(int64_t)j * rp + i] = vi;
       if (i == 0) {
         tdm[j] = buf[j];
@@ -233,32 +260,57 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     // 4. C2 -= v w^T + w v^T on the registers (v, w vanish outside C2), and row j+1 published
     //    for the next step.
     double sq = 0.0;
+    const int jn = __builtin_amdgcn_readfirstlane(j + 1);
+    refresh();
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      const int J = blk ? bB : bA;
-      const bool have = blk ? hasB : hasA;
+      const int J = blkJ(blk);
+      const bool have = blk_has(blk);
       if (!have || J < jb) continue;
       const int b0 = 16 * J + 4 * lc;
-      const double2 v01 = *(const double2*)(vv + b0);
-      const double2 v23 = *(const double2*)(vv + b0 + 2);
-      const double2 w01 = *(const double2*)(wv + b0);
-      const double2 w23 = *(const double2*)(wv + b0 + 2);
-      const double vb[4] = {v01.x, v01.y, v23.x, v23.y};
-      const double wb[4] = {w01.x, w01.y, w23.x, w23.y};
+      double vb[4], wb[4];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        int I, JJ;
-        slot_ij(s, I, JJ);
-        if ((s <= bA) != (blk == 0) || !slot_ok(s)) continue;
-        if (I < jb) continue;
-        const int a = 16 * I + lr;
-        const double va = vv[a], wa = wv[a];
+      for (int q = 0; q < 4; ++q) {
+        const double2 t = vw[b0 + q];
+        vb[q] = t.x;
+        wb[q] = t.y;
+      }
+      const int slo = blk ? bA + 1 : 0, shi = slo + J;   // slots of this block, as above
+      double2 tx[2];
+      tx[0] = tx[1] = vw[16 * J + lr];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) reg[s][q] -= va * wb[q] + wa * vb[q];
-        publish_part(s, j + 1, sq);
+      for (int s = (blk ? NS : SA_END) - 1; s >= blk; --s) {
+        if (s > shi) continue;
+        const int I = s - slo;
+        if (s < slo || I < jb) break;
+        const double2 t = tx[s & 1];
+        tx[(s + 1) & 1] = vw[16 * max(I - 1, 0) + lr];
+        const double va = t.x, wa = t.y;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) reg[s][q] = fma(-va, wb[q], fma(-wa, vb[q], reg[s][q]));
       }
     }
-    publish_sq(j + 1, sq);
+    {
+      // the tiles of row block jn/16: slot jn/16 of block A, slot bA+1+jn/16 of block B
+      const int nbI = jn >> 4;
+      const int sA = (blk_has(0) && nbI <= bA) ? nbI : -1;
+      const int sB = (blk_has(1) && nbI <= nb - 1 - bA) ? bA + 1 + nbI : -1;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (s != sA && s != sB) continue;
+        const int J = (s == sA) ? bA : nb - 1 - bA;
+        if (lr == (jn & 15)) {
+          const int b0 = 16 * J + 4 * lc;
+          double* dst = rowbuf[jn & 1] + b0;
+          *(double2*)dst = double2{reg[s][0], reg[s][1]};
+          *(double2*)(dst + 2) = double2{reg[s][2], reg[s][3]};
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (b0 + q >= jn + 2) sq = fma(reg[s][q], reg[s][q], sq);
+        }
+      }
+    }
+    publish_sq(jn, sq);
   }
   // last 2x2 (or 1x1) block
   if (r >= 2) {
