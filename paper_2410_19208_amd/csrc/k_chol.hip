@@ -6,8 +6,9 @@
 // 16x16 FP64 tiles.  The upper-triangle tiles of G live in registers (tile t in wave t mod 8)
 // in the result layout of v_mfma_f64_16x16x4f64 (lane l holds rows 4v + l/16,
 // column l%16), which is also that instruction's B-operand layout.  For each block column J:
-//   A. the owner of tile (J,J) factors it in registers (lane c holds column c; pivots and row
-//      entries broadcast with readlane) and inverts R_JJ the same way;
+//   A. the owner of tile (J,J) factors it in registers by row operations on [W_JJ | I] (lane c
+//      holds column c of W_JJ, lane 16 + c column c of I; pivots and multipliers broadcast
+//      with readlane), which leaves R_JJ on the left and R_JJ^-T on the right;
 //   B. the panel tiles become R_JK = R_JJ^-T W_JK (MFMA; B operand straight from registers);
 //   C. the trailing tiles take W_KL -= R_JK^T R_JL (MFMA; operands from the panel in LDS).
 // A column whose Schur pivot is below tol * (its Gram diagonal) lies in the span of the
@@ -79,51 +80,51 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
       for (int v = 0; v < 4; ++v) dsm[4 * v + kg][li] = dt[v];
       lds_wave_sync();
+      // Right-looking Cholesky of the tile by row operations on [W | I]: lane c < 16 holds
+      // column c of W, lane 16 + c column c of the identity (lanes >= 32 hold zeros).  Step jj
+      // scales row jj by 1/sqrt(pivot) and subtracts R[jj][i] times it from every row i > jj;
+      // the left half becomes R and the right half R^-T, so lane 16 + i ends with row i of
+      // X = R_JJ^-1, and the inverse costs no broadcasts of its own.  The pivot and the
+      // multipliers R[jj][i] (row jj of lane i) are broadcast with readlane.  A dropped row jj
+      // (1/pivot taken as 0) gives a zero row of R with a unit diagonal and a zero column of X.
       double col[16];
 #pragma unroll
-      for (int a = 0; a < 16; ++a) col[a] = dsm[a][li];   // lanes >= 16 hold copies, unused
-      // right-looking Cholesky of the tile: step jj scales row jj by 1/sqrt(pivot) and updates
-      // the trailing part; pivots and row entries are broadcast with readlane (wave-uniform).
-      // The inverse is built in the same loop, one column per step: lane i holds row i of
-      // X = R_JJ^-1, and X[i][jj] = (delta_ij - sum_{k<jj} X[i][k] R[k][jj]) / R[jj][jj] needs
-      // only column jj of R (final by step jj) and 1/R[jj][jj], so the two dependency chains
-      // run side by side instead of one after the other.  A dropped row jj (zero row of R,
-      // unit pivot, 1/pivot taken as 0) gives a zero row and a zero column of X.
+      for (int a = 0; a < 16; ++a)
+        col[a] = (lane < 16) ? dsm[a][li] : ((lane == 16 + a) ? 1.0 : 0.0);
       int drops = 0;
-      double x[16];
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const double d = bcast_f64(col[jj], jj);
         const double gj = g0[16 * J + jj];
         const bool dr = !(gj > 0.0) || !(d > tol * gj) || !isfinite(d);
-        const double piv = dr ? 0.0 : sqrt(d);
-        // 1/piv: hardware reciprocal refined by two Newton steps (no IEEE division on the chain)
-        double ip = __builtin_amdgcn_rcp(piv);
-        ip = fma(ip, fma(-piv, ip, 1.0), ip);
-        ip = fma(ip, fma(-piv, ip, 1.0), ip);
+        // sqrt(d) and 1/sqrt(d) from the hardware reciprocal-square-root estimate: one
+        // Goldschmidt step, then a Newton correction of each (no IEEE sqrt or division)
+        const double y0 = __builtin_amdgcn_rsq(d);
+        double g = d * y0, h = 0.5 * y0;
+        const double e0 = fma(-h, g, 0.5);
+        g = fma(g, e0, g);
+        h = fma(h, e0, h);
+        g = fma(fma(-g, g, d), h, g);
+        double ip = 2.0 * h;
+        ip = fma(ip, fma(-g, ip, 1.0), ip);
+        const double piv = dr ? 0.0 : g;
         ip = dr ? 0.0 : ip;
-        const double rowv = (lane > jj) ? col[jj] * ip : 0.0;   // R[jj][c], c = lane
+        const double nrm = col[jj] * ip;   // row jj scaled; R[jj][c] in lane c > jj
 #pragma unroll
-        for (int a = jj + 1; a < 16; ++a) col[a] -= bcast_f64(rowv, a) * rowv;
-        col[jj] = (lane > jj) ? rowv : (lane == jj ? (dr ? 1.0 : piv) : col[jj]);
+        for (int a = jj + 1; a < 16; ++a) col[a] -= bcast_f64(nrm, a) * nrm;
+        col[jj] = (lane == jj) ? (dr ? 1.0 : piv) : nrm;
         drops |= (dr ? 1 : 0) << jj;
-        // column jj of X; R[k][jj] (k < jj) is col[k] of lane jj
-        double acc = (lane == jj) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < jj; ++k) acc -= x[k] * bcast_f64(col[k], jj);
-        x[jj] = (lane > jj) ? 0.0 : acc * ip;
-        __builtin_amdgcn_sched_barrier(0);   // keep the broadcasts of one step together
       }
-      // R_JJ (upper, zero below; lane c holds column c) and its inverse (lane i holds row i) to
-      // LDS; R_JJ back to the owner's registers
+      // R_JJ (upper, zero below; lane c holds column c) and its inverse (lane 16 + i holds row i)
+      // to LDS; R_JJ back to the owner's registers
       lds_wave_sync();
       if (lane < 16) {
 #pragma unroll
-        for (int a = 0; a < 16; ++a) {
-          dsm[a][lane] = (a <= lane) ? col[a] : 0.0;
-          dinv[lane][a] = x[a];
-        }
+        for (int a = 0; a < 16; ++a) dsm[a][lane] = (a <= lane) ? col[a] : 0.0;
         dflag[16 * J + lane] = (drops >> lane) & 1;
+      } else if (lane < 32) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) dinv[lane - 16][a] = col[a];
       }
       lds_wave_sync();
 #pragma unroll
