@@ -56,13 +56,19 @@ __device__ __forceinline__ void reduce_scatter(double (&x)[RB], int lane) {
 }
 
 // Fixed-order sum of the nb contributions of block row b, shift, store, sum of squares; the
-// last block row also forms the norm.
+// last block row also forms the norm.  The contributions are loaded FIN_CHUNK at a time (all
+// issued before the first is added, from clamped addresses) and added in block order; the
+// last block row's threads load the nb row sums of squares in parallel and thread 0 adds them
+// in block order from LDS.
+constexpr int FIN_CHUNK = 32;
 __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __restrict__ probs,
                                                               const int* __restrict__ tstart, int nprob, int last) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int b = blockIdx.x - tstart[pi];
   __shared__ double red[GEMV_THREADS / WAVE];
+  __shared__ double rows[GEMV_THREADS];
+  __shared__ int is_last;
   const int n = p.n, ld = p.ld;
   const int nb = (n + GEMV_TILE - 1) / GEMV_TILE;
   const int pp = p.iscal[I_PP] & 1;
@@ -76,8 +82,14 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __rest
   double y = 0.0;
   if (row < n) {
     double s = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < nb; ++c) s += part[(int64_t)c * GEMV_TILE + x];
+    for (int c0 = 0; c0 < nb; c0 += FIN_CHUNK) {
+      double t[FIN_CHUNK];
+#pragma unroll
+      for (int k = 0; k < FIN_CHUNK; ++k) t[k] = part[(int64_t)min(c0 + k, nb - 1) * GEMV_TILE + x];
+#pragma unroll
+      for (int k = 0; k < FIN_CHUNK; ++k)
+        if (c0 + k < nb) s += t[k];
+    }
     y = s - shift * (vin[row] * inv);
     vout[row] = y;
   }
@@ -89,20 +101,27 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __rest
     for (int w = 0; w < GEMV_THREADS / WAVE; ++w) tot += red[w];
     p.vpart[b] = tot;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const int ticket = atomicAdd(&p.iscal[I_COUNTER], 1);
-    if (ticket == nb - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const double* vp = p.vpart;
-      double t2 = 0.0;
-      for (int r = 0; r < nb; ++r) t2 += vp[r];
-      const double nrm = sqrt(t2);
-      p.scal[S_NRM] = nrm;
-      p.scal[S_INV] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
-      if (last == 1) p.scal[S_SIGMA1] = nrm;
-      if (last == 2) p.scal[S_SIGMA2] = nrm;
-      p.iscal[I_COUNTER] = 0;
-      p.iscal[I_PP] = p.iscal[I_PP] + 1;
-    }
+    is_last = (atomicAdd(&p.iscal[I_COUNTER], 1) == nb - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double t2 = 0.0;
+  for (int r0 = 0; r0 < nb; r0 += GEMV_THREADS) {
+    if (r0 + x < nb) rows[x] = p.vpart[r0 + x];
+    __syncthreads();
+    if (x == 0)
+      for (int r = 0; r < GEMV_THREADS && r0 + r < nb; ++r) t2 += rows[r];
+    __syncthreads();
+  }
+  if (x == 0) {
+    const double nrm = sqrt(t2);
+    p.scal[S_NRM] = nrm;
+    p.scal[S_INV] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+    if (last == 1) p.scal[S_SIGMA1] = nrm;
+    if (last == 2) p.scal[S_SIGMA2] = nrm;
+    p.iscal[I_COUNTER] = 0;
+    p.iscal[I_PP] = p.iscal[I_PP] + 1;
   }
 }
 
