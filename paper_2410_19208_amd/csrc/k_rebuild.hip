@@ -234,7 +234,8 @@ __device__ void rebuild_tile(const Prob& p, int I, int J) {
       if (R0 + i >= n) continue;
       const T* src = half + i * LDT + c;
       if (!diag && J0 + c + 3 < n && sizeof(T) == 4) {
-        *(gmem<f32x4>*)(P + (int64_t)(R0 + i) * ldp + J0 + c) = f32x4{(float)src[0], (float)src[1], (float)src[2], (float)src[3]};
+        __builtin_nontemporal_store(f32x4{(float)src[0], (float)src[1], (float)src[2], (float)src[3]},
+                                    (gmem<f32x4>*)(P + (int64_t)(R0 + i) * ldp + J0 + c));
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -248,7 +249,8 @@ __device__ void rebuild_tile(const Prob& p, int I, int J) {
       if (J0 + j >= n) continue;
       const T x[4] = {half[i * LDT + j], half[(i + 1) * LDT + j], half[(i + 2) * LDT + j], half[(i + 3) * LDT + j]};
       if (!diag && R0 + i + 3 < n && sizeof(T) == 4) {
-        *(gmem<f32x4>*)(P + (int64_t)(J0 + j) * ldp + R0 + i) = f32x4{(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
+        __builtin_nontemporal_store(f32x4{(float)x[0], (float)x[1], (float)x[2], (float)x[3]},
+                                    (gmem<f32x4>*)(P + (int64_t)(J0 + j) * ldp + R0 + i));
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
