@@ -29,6 +29,7 @@ METRIC = "PSD projections/s + TFLOP/s & HBM GB/s at n=20K,k=200; p50/p99 latency
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large_20k_bf16x3.md")
@@ -223,9 +224,17 @@ def main() -> int:
         units = 2 * (args.alpha_iters + 1)
         note = "upper triangle of the symmetric A read once per product plus two FP64 vectors"
     elif dom == "k_pass":
-        per_unit = nn * es  # A streamed once per pass (the Z panel is L2/MALL resident)
+        # Matrix-core bound: the problems of a grouped launch that stream the same A share its
+        # reads in L2 (tile pairing), so HBM is not the binding resource.  Algorithmic flops per
+        # problem-pass: the products the precision's scheme needs, 2 n^2 r each (BF16x3: the
+        # three BF16 products hi*hi, hi*lo, lo*hi).
+        nprod, peak = {"bf16x3": (3, BF16_PEAK_TFLOPS), "fp32": (1, FP32_PEAK_TFLOPS),
+                       "fp64": (1, FP64_PEAK_TFLOPS)}[args.precision]
+        bound, unit = "mfma", "TFLOP/s"
+        per_unit = nprod * 2 * nn * r
         units = 2 * passes
-        note = "A read once per pass and problem"
+        note = (f"{nprod} matrix-core product(s) of 2 n^2 r flops per pass and problem, "
+                f"r = k + p = {r}; {args.precision} peak")
     elif dom == "k_rebuild":
         per_unit = nn * es
         units = 2
@@ -234,26 +243,31 @@ def main() -> int:
         per_unit, units = float("nan"), 1
         note = "no algorithmic byte model for this kernel"
     alg = per_unit * units / launches_per_step
-    achieved = alg / (d["avg_us"] * 1e-6) / 1e9
+    achieved = alg / (d["avg_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
     traffic = measured_traffic(dom, units / launches_per_step)
     roofline = {"bound": bound, "kernel": dom, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": traffic, "algorithmic_bytes_per_launch": alg,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                ("algorithmic_flops_per_launch" if unit == "TFLOP/s" else "algorithmic_bytes_per_launch"): alg,
                 "problems_per_launch": round(units / launches_per_step, 3),
                 "avg_launch_us": round(d["avg_us"], 2), "model": note}
 
-    # every A-streaming kernel against the HBM roofline (algorithmic bytes per launch)
+    # every A-streaming kernel against the HBM roofline (algorithmic bytes per launch).  A pass
+    # launch reads A once whether it covers one problem or the two problems of the step, which
+    # stream the same A and share its reads.
     streaming = {}
-    for kname, per, units_step in (("k_pass", nn * es, 2 * passes),
-                                   ("k_gemv", n * (n + 1) / 2 * es + 2 * n * 8.0, 2 * (args.alpha_iters + 1)),
-                                   ("k_rebuild", nn * es, 2)):
+    for kname, per_launch, per_problem, problems_step in (
+            ("k_pass", nn * es, None, 2 * passes),
+            ("k_gemv", None, n * (n + 1) / 2 * es + 2 * n * 8.0, 2 * (args.alpha_iters + 1)),
+            ("k_rebuild", None, nn * es, 2)):
         if kname in kern:
             kd = kern[kname]
             lps = kd["launches"] / args.steps
-            b = per * units_step / lps
+            ppl = problems_step / lps
+            b = per_launch if per_launch is not None else per_problem * ppl
             gbs = b / (kd["avg_us"] * 1e-6) / 1e9
             streaming[kname] = {"gb_per_launch": round(b / 1e9, 4), "avg_us": round(kd["avg_us"], 2),
                                 "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
-                                "traffic_bytes": measured_traffic(kname, units_step / lps)}
+                                "traffic_bytes": measured_traffic(kname, ppl)}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "projections/s", "n_gpus": 1, "steps": args.steps,

@@ -483,9 +483,20 @@ __global__ __launch_bounds__(PASS_BM_F / (16 * VB) * 64, 1)
 void k_pass_b3(const Prob* __restrict__ probs, const int* __restrict__ tstart, int nprob) {
   static_assert(NCB % 2 == 0, "panel widths are multiples of 32 columns");
   extern __shared__ __attribute__((aligned(1024))) unsigned char smem[];
-  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  int pi, t;
+  if (nprob == 2 && probs[0].A == probs[1].A && probs[0].lda == probs[1].lda && probs[0].n == probs[1].n &&
+      probs[0].split == probs[1].split && tstart[0] == 0 && tstart[1] == tstart[2] - tstart[1]) {
+    // Two problems streaming the same A with the same tiling: tile t of both runs on the same
+    // XCD (workgroup b runs on XCD b mod 8) one group of 8 workgroups apart, so the two reads
+    // of each A slice meet in that XCD's L2 and HBM serves one.
+    const int b = blockIdx.x, g = b >> 4, w = b & 15;
+    pi = w >> 3;
+    t = 8 * g + (w & 7);
+  } else {
+    pi = find_prob(tstart, nprob, blockIdx.x);
+    t = blockIdx.x - tstart[pi];
+  }
   const Prob& p = probs[pi];
-  const int t = blockIdx.x - tstart[pi];
   if (t >= p.npass_tiles) return;
   if (p.avec) pass_b3_tile<NCB, VB, true>(p, t, smem);
   else pass_b3_tile<NCB, VB, false>(p, t, smem);
