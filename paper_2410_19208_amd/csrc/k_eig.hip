@@ -6,11 +6,12 @@
 //              threshold (0 plain, 1 scaled), so only the r - nu kept eigenpairs get vectors.
 //  k_bisect  : every eigenvalue of T by multisection of Sturm counts, one wave per eigenvalue
 //              (64 trial points per round).
-//  k_invit   : eigenvectors of the kept eigenvalues by inverse iteration on T (tridiagonal LU
-//              with partial pivoting), Gram-Schmidt within clusters of close eigenvalues,
-//              back-transformation by the Householder reflectors, and the clamped weights.
-//              Writes V (column c = c-th largest kept eigenvalue, column-major) and
-//              F = V diag(sqrt(w)) (row-major).
+//  k_invit   : eigenvectors of T for the kept eigenvalues by inverse iteration (tridiagonal LU
+//              with partial pivoting), Gram-Schmidt within clusters of close eigenvalues, and
+//              the clamped weights; the vectors of T go to xt.
+//  k_backxf  : back-transformation of each by the Householder reflectors, one wave per
+//              eigenvector.  Writes V (column c = c-th largest kept eigenvalue, column-major)
+//              and F = V diag(sqrt(w)) (row-major).
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -117,17 +118,32 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
   const bool scaled = (p.variant == PSDPROJ_SCALED);
   const double alpha = p.scal[S_ALPHA];
 
-  // weights and r_plus (one thread per problem; read by later kernels)
-  if (blockIdx.x == tstart[pi] && threadIdx.x == 0) {
-    int rplus = 0;
-    for (int jj = r - 1; jj >= nu; --jj) {
-      const double lam = p.evals[jj];
-      const double wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
-      if (wgt > 0.0 && isfinite(wgt)) p.wts[rplus++] = wgt;
-      else break;
+  // weights and r_plus (the first wave of each problem; read by later kernels): weight c is
+  // that of eigenvalue r-1-c, and r_plus counts the leading positive finite weights down to
+  // eigenvalue nu.  Lanes take 64 weights at a time; a ballot finds the first that fails.
+  if (blockIdx.x == tstart[pi]) {
+    int rplus = rp;
+    double wv[(PSDPROJ_MAX_RANK + WAVE - 1) / WAVE];
+#pragma unroll
+    for (int c0 = 0, u = 0; c0 < PSDPROJ_MAX_RANK; c0 += WAVE, ++u) {
+      const int c = c0 + lane, jj = r - 1 - c;
+      double wgt = 0.0;
+      bool ok = false;
+      if (c < rp && jj >= nu) {
+        const double lam = p.evals[jj];
+        wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
+        ok = wgt > 0.0 && isfinite(wgt);
+      }
+      wv[u] = wgt;
+      const unsigned long long bad = __ballot(!ok);
+      if (bad != 0ull) rplus = min(rplus, c0 + __ffsll((long long)bad) - 1);
     }
-    for (int c = rplus; c < rp; ++c) p.wts[c] = 0.0;
-    p.iscal[I_RPLUS] = rplus;
+#pragma unroll
+    for (int c0 = 0, u = 0; c0 < PSDPROJ_MAX_RANK; c0 += WAVE, ++u) {
+      const int c = c0 + lane;
+      if (c < rp) p.wts[c] = (c < rplus) ? wv[u] : 0.0;
+    }
+    if (lane == 0) p.iscal[I_RPLUS] = rplus;
   }
   if (j0 >= r) return;
   const double gtol = 1e-5 * tnorm;
@@ -153,26 +169,32 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
   int jc = j0;
   do {
     const double lam = p.evals[jc];
-    // --- LU of T - lam I with partial pivoting (all lanes compute the same values and store
-    // the same entries)
+    // --- LU of T - lam I with partial pivoting (all lanes compute the same values; lane 0
+    // stores them).  Branch-free step: the pivot is chosen by a compare and selects, and
+    // 1/pivot is the refined hardware reciprocal (IEEE division only for a pivot below the
+    // normal range, the same in all lanes).
     {
       double cd = dl[0] - lam, cs = (r > 1) ? el[0] : 0.0;
       for (int i = 0; i + 1 < r; ++i) {
         const double nd = dl[i + 1] - lam;
         const double ns = (i + 2 < r) ? el[i + 1] : 0.0;
         const double sb = el[i];
-        if (fabs(cd) >= fabs(sb)) {
-          if (cd == 0.0) cd = tiny;
-          const double m = sb / cd;
-          U0[i] = cd; U1[i] = cs; U2[i] = 0.0; Lm[i] = m; piv[i] = 0;
-          cd = nd - m * cs;
-          cs = ns;
-        } else {
-          const double m = cd / sb;
-          U0[i] = sb; U1[i] = nd; U2[i] = ns; Lm[i] = m; piv[i] = 1;
-          cd = cs - m * nd;
-          cs = -m * ns;
+        const bool keep = fabs(cd) >= fabs(sb);
+        const double pv = keep ? ((cd == 0.0) ? tiny : cd) : sb;
+        const double num = keep ? sb : cd;
+        double m;
+        if (fabs(pv) >= 2.2250738585072014e-308) m = num * rcp_f64(pv);
+        else m = num / pv;
+        if (lane == 0) {   // one lane stores (64 lanes writing one address serialise)
+          U0[i] = pv;
+          U1[i] = keep ? cs : nd;
+          U2[i] = keep ? 0.0 : ns;
+          Lm[i] = m;
+          piv[i] = keep ? 0 : 1;
         }
+        const double ncd = keep ? nd - m * cs : cs - m * nd;
+        cs = keep ? ns : -m * ns;
+        cd = ncd;
       }
       if (cd == 0.0) cd = tiny;
       if (lane == 0) U0[r - 1] = cd;
@@ -184,16 +206,33 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
     }
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
-      // --- solve (T - lam I) x = b: forward with row swaps, then back substitution (lane 0)
-      // (the running entries stay in registers, so each step waits only on its multiply-add)
+      // --- solve (T - lam I) x = b: forward with row swaps, then back substitution (lane 0).
+      // The running entries stay in registers; the LDS operands are read in chunks of SC
+      // steps ahead of the chain, so each step waits only on its multiply-add.
       if (lane == 0) {
+        constexpr int SC = 8;
         double cur = b[0];
-        for (int i = 0; i + 1 < r; ++i) {
-          double nxt = b[i + 1];
-          if (piv[i]) { const double t = cur; cur = nxt; nxt = t; }
-          nxt -= Lm[i] * cur;
-          b[i] = cur;
-          cur = nxt;
+        for (int i0 = 0; i0 + 1 < r; i0 += SC) {
+          double bn[SC], lm[SC];
+          int pw[SC];
+#pragma unroll
+          for (int k = 0; k < SC; ++k) {
+            const int i = min(i0 + k, r - 2);
+            bn[k] = b[i + 1];
+            lm[k] = Lm[i];
+            pw[k] = piv[i];
+          }
+#pragma unroll
+          for (int k = 0; k < SC; ++k) {
+            const int i = i0 + k;
+            if (i + 1 < r) {
+              double nxt = bn[k];
+              if (pw[k]) { const double t = cur; cur = nxt; nxt = t; }
+              nxt -= lm[k] * cur;
+              b[i] = cur;
+              cur = nxt;
+            }
+          }
         }
         b[r - 1] = cur;
         double x1 = b[r - 1] * iu0[r - 1], x2 = 0.0;
@@ -204,11 +243,26 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
           x2 = x1;
           x1 = x0;
         }
-        for (int i = r - 3; i >= 0; --i) {
-          const double x0 = (b[i] - U1[i] * x1 - U2[i] * x2) * iu0[i];
-          x[i] = x0;
-          x2 = x1;
-          x1 = x0;
+        for (int i0 = r - 3; i0 >= 0; i0 -= SC) {
+          double bb[SC], u1[SC], u2[SC], iu[SC];
+#pragma unroll
+          for (int k = 0; k < SC; ++k) {
+            const int i = max(i0 - k, 0);
+            bb[k] = b[i];
+            u1[k] = U1[i];
+            u2[k] = U2[i];
+            iu[k] = iu0[i];
+          }
+#pragma unroll
+          for (int k = 0; k < SC; ++k) {
+            const int i = i0 - k;
+            if (i >= 0) {
+              const double x0 = (bb[k] - u1[k] * x1 - u2[k] * x2) * iu[k];
+              x[i] = x0;
+              x2 = x1;
+              x1 = x0;
+            }
+          }
         }
       }
       __syncthreads();
@@ -233,54 +287,84 @@ __global__ __launch_bounds__(WAVE) void k_invit(const Prob* __restrict__ probs,
       for (int i = lane; i < r; i += WAVE) b[i] = x[i] * sc;
       __syncthreads();
     }
-    // b holds the unit eigenvector of T; keep it for later cluster members
+    // b holds the unit eigenvector of T: kept for later cluster members and for k_backxf
     gmem<double>* xs = xt + (int64_t)(jc - nu) * rp;
     for (int i = lane; i < r; i += WAVE) xs[i] = b[i];
-    // --- back-transform u = H_0 H_1 ... H_{r-3} b, in registers: lane l holds entries
-    // l + 64 q (q < 4); the next reflector's column is loaded while the current one is applied
-    double bv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) bv[q] = (lane + 64 * q < r) ? b[lane + 64 * q] : 0.0;
-    const gmem<const double>* Hc = gp((const double*)p.H);
-    auto hload = [&](int jh, double (&h)[4]) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) h[q] = Hc[(int64_t)jh * rp + min(lane + 64 * q, rp - 1)];
-    };
-    double hc[4], hn[4];
-    if (r >= 3) hload(r - 3, hc);
-    for (int jh = r - 3; jh >= 0; --jh) {
-      if (jh > 0) hload(jh - 1, hn);
-      const double tau = p.tau[jh];
-      double v[4], s = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = lane + 64 * q;
-        v[q] = (i == jh + 1) ? 1.0 : ((i > jh + 1 && i < r) ? hc[q] : 0.0);
-        s += v[q] * bv[q];
-      }
-      s = wave_allsum(s) * tau;   // tau = 0: identity reflector
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] -= s * v[q];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) hc[q] = hn[q];
-    }
-    // --- store: column c = r-1-jc (descending eigenvalue order)
-    const int c = r - 1 - jc;
-    const double wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
-    const double sw = (wgt > 0.0 && isfinite(wgt)) ? sqrt(wgt) : 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = lane + 64 * q;
-      if (i < rp) {
-        const double u = (i < r) ? bv[q] : 0.0;
-        p.V[(int64_t)c * rp + i] = u;
-        p.F[(int64_t)i * rp + c] = u * sw;   // row-major (read by the factor apply)
-      }
-    }
     __syncthreads();
     ++jc;
   } while (jc < r && p.evals[jc] - p.evals[jc - 1] <= gtol);
   (void)thr;
+}
+
+// Back-transformation u = H_0 H_1 ... H_{r-3} y of every kept eigenvector y of T (left in xt
+// by k_invit), one wave per eigenvector, so the members of a cluster, found one after another
+// by their leader, are transformed side by side.  Lane l holds entries l + 64 q (q < 4) in
+// registers; the next reflector's column is loaded while the current one is applied.  Writes
+// column c = r-1-j of V (column-major) and row-major F = V diag(sqrt(w)).
+__global__ __launch_bounds__(WAVE) void k_backxf(const Prob* __restrict__ probs,
+                                                 const int* __restrict__ tstart, int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int lane = threadIdx.x;
+  const int r = p.r, rp = p.rpad;
+  const int nu = p.iscal[I_NU];
+  const int jc = nu + (blockIdx.x - tstart[pi]);
+  if (jc >= r) return;
+  const bool scaled = (p.variant == PSDPROJ_SCALED);
+  const double alpha = p.scal[S_ALPHA];
+  const double lam = p.evals[jc];
+  const gmem<const double>* xs = gp((const double*)p.xt) + (int64_t)(jc - nu) * rp;
+  double bv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bv[q] = (lane + 64 * q < r) ? xs[lane + 64 * q] : 0.0;
+  // Reflector columns (and their tau) stream through a ring of BX register slots: slot k is
+  // refilled with the reflector BX steps further on as soon as it has been applied, so a
+  // column's load has BX reflectors' worth of work to hide behind.
+  constexpr int BX = 8;
+  const gmem<const double>* Hc = gp((const double*)p.H);
+  const gmem<const double>* Tc = gp((const double*)p.tau);
+  double hr[BX][4], tr[BX];
+  auto hload = [&](int jh, double (&h)[4], double& t) {
+    jh = max(jh, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = Hc[(int64_t)jh * rp + min(lane + 64 * q, rp - 1)];
+    t = Tc[jh];
+  };
+#pragma unroll
+  for (int k = 0; k < BX; ++k) hload(r - 3 - k, hr[k], tr[k]);
+  for (int base = r - 3; base >= 0; base -= BX) {
+#pragma unroll
+    for (int k = 0; k < BX; ++k) {
+      const int jh = base - k;
+      if (jh >= 0) {
+        const double tau = tr[k];
+        double v[4], sdot = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = lane + 64 * q;
+          v[q] = (i == jh + 1) ? 1.0 : ((i > jh + 1 && i < r) ? hr[k][q] : 0.0);
+          sdot += v[q] * bv[q];
+        }
+        sdot = wave_allsum(sdot) * tau;   // tau = 0: identity reflector
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bv[q] -= sdot * v[q];
+      }
+      hload(base - k - BX, hr[k], tr[k]);
+    }
+  }
+  // column c = r-1-jc (descending eigenvalue order)
+  const int c = r - 1 - jc;
+  const double wgt = scaled ? alpha * (fmax(lam, 1.0) - 1.0) : fmax(lam, 0.0);
+  const double sw = (wgt > 0.0 && isfinite(wgt)) ? sqrt(wgt) : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = lane + 64 * q;
+    if (i < rp) {
+      const double u = (i < r) ? bv[q] : 0.0;
+      p.V[(int64_t)c * rp + i] = u;
+      p.F[(int64_t)i * rp + c] = u * sw;   // row-major (read by the factor apply)
+    }
+  }
 }
 
 int tiles_bisect(const Prob& p) { return (p.r + 3) / 4; }
@@ -291,6 +375,9 @@ void launch_bisect(const Launch& L) {
 }
 void launch_invit(const Launch& L) {
   hipLaunchKernelGGL(k_invit, dim3(L.grid), dim3(WAVE), 0, L.stream, L.probs, L.tstart, L.nprob);
+}
+void launch_backxf(const Launch& L) {
+  hipLaunchKernelGGL(k_backxf, dim3(L.grid), dim3(WAVE), 0, L.stream, L.probs, L.tstart, L.nprob);
 }
 
 }  // namespace psd

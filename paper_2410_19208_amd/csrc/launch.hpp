@@ -53,6 +53,7 @@ void apply_init();
 void launch_tridiag(const Launch& L);
 void launch_bisect(const Launch& L);
 void launch_invit(const Launch& L);
+void launch_backxf(const Launch& L);
 void launch_formw(const Launch& L);
 void launch_rebuild(const Launch& L, int prec);
 void rebuild_init();

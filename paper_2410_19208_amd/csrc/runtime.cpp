@@ -165,7 +165,7 @@ static int stage_tiles(const Prob& p, int kind) {
     case K_GRED: return (int)(((int64_t)p.rpad * p.rpad + 255) / 256);
     case K_APPLY: case K_FACTOR: return tiles_apply(p);
     case K_BISECT: return tiles_bisect(p);
-    case K_INVIT: return tiles_invit(p);
+    case K_INVIT: case K_BACKXF: return tiles_invit(p);
     case K_REBUILD: return tiles_rebuild(p);
   }
   return 0;
@@ -211,6 +211,7 @@ static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
   add(K_TRIDIAG, 0, W_ALL, 0);
   add(K_BISECT, 0, W_ALL, 0);
   add(K_INVIT, 0, W_ALL, 0);
+  add(K_BACKXF, 0, W_ALL, 0);
   add(K_FACTOR, 2, W_ALL, 0);
   add(K_REBUILD, 0, W_ALL, 0);
   add(K_FINAL, 0, W_ALL, 0);
@@ -398,6 +399,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
       case K_TRIDIAG: launch_tridiag(L); break;
       case K_BISECT: launch_bisect(L); break;
       case K_INVIT: launch_invit(L); break;
+      case K_BACKXF: launch_backxf(L); break;
       case K_REBUILD: launch_rebuild(L, R.prec); break;
       case K_FINAL: launch_finalize(L); break;
     }
@@ -415,7 +417,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
 static const char* const KIND_NAMES[K_NKINDS] = {
     "k_setup", "k_omega", "k_power_init", "k_gemv", "k_alpha", "k_pass", "k_pass_reduce", "k_gram",
     "k_gram_full", "k_gram_reduce", "k_chol", "k_apply", "k_tridiag", "k_bisect", "k_invit", "k_rebuild",
-    "k_finalize", "k_gemv_finish", "k_apply_factor"};
+    "k_finalize", "k_gemv_finish", "k_apply_factor", "k_backxf"};
 
 psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp) {
   const int64_t n = pl.d.n;

@@ -22,7 +22,7 @@ struct Plan {
 
 enum Kind {
   K_SETUP, K_OMEGA, K_PINIT, K_GEMV, K_ALPHA, K_PASS, K_PRED, K_GRAM_SYM, K_GRAM_FULL, K_GRED,
-  K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_GEMV_FIN, K_FACTOR, K_NKINDS
+  K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_GEMV_FIN, K_FACTOR, K_BACKXF, K_NKINDS
 };
 enum When { W_ALL, W_ALPHA, W_ALPHA_ITER, W_POWER };
 
