@@ -188,8 +188,13 @@ psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t star
 /* Kernel timing (tracing aid, off by default).  While enabled, every launch of the library
  * is bracketed by HIP events recorded on the launch stream; psdproj_profile_read waits for
  * them and returns the accumulated device time and launch count of one kernel kind
- * (0 <= kind < psdproj_kernel_kinds(); psdproj_kernel_name gives the kernel's symbol stem). */
+ * (0 <= kind < psdproj_kernel_kinds(); psdproj_kernel_name gives the kernel's symbol stem).
+ * psdproj_profile_select restricts the timing to the kinds whose bit is set in `kinds`
+ * (bit k for kind k; all kinds until it is called; bits past the last kind are ignored).
+ * Each timed launch adds two event records to its stream, which lengthen a step of many
+ * short launches, so a throughput measurement times only the kinds it reports. */
 psdproj_status psdproj_profile_enable(int32_t enable);
+psdproj_status psdproj_profile_select(uint64_t kinds);
 psdproj_status psdproj_profile_reset(void);
 psdproj_status psdproj_profile_read(int32_t kind, double* total_ms, int64_t* launches);
 int32_t        psdproj_kernel_kinds(void);

@@ -83,6 +83,7 @@ _SIGS = {
     "psdproj_philox_words": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
     "psdproj_gaussian": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
     "psdproj_profile_enable": (_i32, [_i32]),
+    "psdproj_profile_select": (_i32, [ctypes.c_uint64]),
     "psdproj_profile_reset": (_i32, []),
     "psdproj_profile_read": (_i32, [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]),
     "psdproj_kernel_kinds": (_i32, []),
@@ -103,6 +104,12 @@ for _name, (_res, _args) in _SIGS.items():
 
 def psdproj_profile_enable(enable: bool = True) -> None:
     _check(lib.psdproj_profile_enable(1 if enable else 0), "psdproj_profile_enable")
+
+
+def psdproj_profile_select(kinds) -> None:
+    """Time only the given kernel kinds (an iterable of kind numbers), or every kind (None)."""
+    mask = (1 << 64) - 1 if kinds is None else sum(1 << int(k) for k in kinds)
+    _check(lib.psdproj_profile_select(ctypes.c_uint64(mask)), "psdproj_profile_select")
 
 
 def psdproj_profile_reset() -> None:

@@ -334,6 +334,7 @@ namespace {
 struct Prof {
   std::mutex mu;
   bool on = false;
+  uint64_t kinds = ~0ull;   // kinds timed while on (bit k: kind k)
   struct Pending { int kind; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
@@ -368,14 +369,17 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
   const int* tdev = (const int*)(hdr + s.prob_bytes);
   Prof& PR = prof();
   std::unique_lock<std::mutex> plock(PR.mu, std::defer_lock);
-  bool timing = false;
+  bool timing_on = false;
+  uint64_t timed_kinds = 0;
   {
     std::lock_guard<std::mutex> g(PR.mu);
-    timing = PR.on;
+    timing_on = PR.on;
+    timed_kinds = PR.kinds;
   }
   for (const LaunchRec& R : s.launches) {
     Launch L{R.grid, probs + R.first, tdev + R.toff, R.count, stream, R.maxnb};
     hipEvent_t ea = nullptr, eb = nullptr;
+    const bool timing = timing_on && ((timed_kinds >> R.kind) & 1ull);
     if (timing) {
       plock.lock();
       ea = PR.get();
@@ -573,6 +577,13 @@ psdproj_status psdproj_profile_enable(int32_t enable) {
   Prof& P = prof();
   std::lock_guard<std::mutex> g(P.mu);
   P.on = enable != 0;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_profile_select(uint64_t kinds) {
+  Prof& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.kinds = kinds;
   return PSDPROJ_OK;
 }
 
