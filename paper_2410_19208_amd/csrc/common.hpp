@@ -48,7 +48,15 @@ constexpr int NISCAL = 16;
 enum { S_ALPHA = 0, S_SIGMA1 = 1, S_SIGMA2 = 2, S_NRM = 3, S_INV = 4, S_SHIFT = 5, S_TNORM = 6,
        S_THRESH = 7 };
 // iscal[] slots
-enum { I_STATUS = 0, I_RPLUS = 1, I_NU = 2, I_COUNTER = 3, I_NEWTON = 4, I_NDROP = 5, I_PP = 6 };
+enum { I_STATUS = 0, I_RPLUS = 1, I_NU = 2, I_COUNTER = 3, I_NEWTON = 4, I_NDROP = 5, I_PP = 6, I_WELL = 7 };
+
+// Stage argument of the CholeskyQR2 kernels (Gram, its reduce, Cholesky, apply): the round
+// (0 or 1) in the low 4 bits, and 16 (o + 1) with o the step's position in the problem's
+// sequence of 1 + 2q orthonormalisations (0 when unknown).  Every step but the last only
+// needs the range of its input: when the first round's Cholesky finds the input well
+// conditioned (I_WELL), its Q = Y R^-1 is already orthonormal to far better than the pass
+// precision and the second round is skipped.  The last step always runs both rounds.
+constexpr int ORTH_ROUND_MASK = 15;
 
 // Per-problem descriptor, resident in device memory (workspace header).
 struct Prob {
@@ -79,6 +87,12 @@ struct Prob {
   int32_t* drop;                   // rpad flags
   psdproj_result* res;
 };
+
+__device__ __forceinline__ bool orth_single(const Prob& p, int arg) {
+  const int o = (arg >> 4) - 1;
+  return o >= 0 && o < 2 * p.q && p.iscal[I_WELL] != 0;
+}
+
 
 // Row (within a 16x16 output block) of accumulator slot v held by a lane of group kg = lane/16:
 // the FP32/BF16 16x16 MFMAs hold rows 4*kg + v, the FP64 16x16x4 MFMA holds rows 4*v + kg.

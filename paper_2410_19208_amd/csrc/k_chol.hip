@@ -27,15 +27,21 @@
 namespace psd {
 
 constexpr int CH_WAVES = 8;
+// Every Schur pivot at least CQ_WELL times its Gram diagonal: the column-scaled condition
+// number of Y is then at most about sqrt(r / CQ_WELL), and Q = Y R^-1 is orthonormal to about
+// r eps / CQ_WELL, so one CholeskyQR round suffices where only the range is needed.
+constexpr double CQ_WELL = 1e-6;
 constexpr int CH_THREADS = CH_WAVES * WAVE;
 constexpr int NBMAX = PSDPROJ_MAX_RANK / 16;
 
 // NS register slots per wave: 14 cover r_pad <= 224 (105 tiles), 17 cover r_pad = 256 (136).
 template <int NS>
 __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                     int nprob, int round) {
+                                                     int nprob, int arg) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
+  const int round = arg & ORTH_ROUND_MASK;
+  if (round == 1 && orth_single(p, arg)) return;   // second CholeskyQR round not needed
   const int r = p.r, rp = p.rpad, nb = rp / 16, nt = nb * (nb + 1) / 2;
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63, li = lane & 15, kg = lane >> 4;
   const gmem<const double>* __restrict__ G = gp((const double*)p.G);
@@ -46,6 +52,7 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
   __shared__ double dinv[16][17];           // R_JJ^-1
   __shared__ double g0[PSDPROJ_MAX_RANK];
   __shared__ int dflag[PSDPROJ_MAX_RANK];
+  __shared__ int wflag[PSDPROJ_MAX_RANK];   // Schur pivot below CQ_WELL x Gram diagonal
   const double tol = (p.prec == F64) ? 1e-26 : 1e-13;
 
   for (int j = tid; j < rp; j += CH_THREADS) g0[j] = (j < r) ? G[(int64_t)j * rp + j] : 0.0;
@@ -122,6 +129,9 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
 #pragma unroll
         for (int a = 0; a < 16; ++a) dsm[a][lane] = (a <= lane) ? col[a] : 0.0;
         dflag[16 * J + lane] = (drops >> lane) & 1;
+        // the Schur pivot of column lane is R[lane][lane]^2 (read back from this lane's store)
+        const double rjj = dsm[lane][lane];
+        wflag[16 * J + lane] = (rjj * rjj >= CQ_WELL * g0[16 * J + lane]) ? 0 : 1;
       } else if (lane < 32) {
 #pragma unroll
         for (int a = 0; a < 16; ++a) dinv[lane - 16][a] = col[a];
@@ -192,11 +202,14 @@ __global__ __launch_bounds__(CH_THREADS) void k_chol(const Prob* __restrict__ pr
   }
   lds_barrier();
   if (tid == 0) {
-    int ndrop = 0;
-    for (int j = 0; j < r; ++j) ndrop += dflag[j];
+    int ndrop = 0, nweak = 0;
+    for (int j = 0; j < r; ++j) {
+      ndrop += dflag[j];
+      nweak += dflag[j] | wflag[j];
+    }
     p.iscal[I_NDROP] = ndrop;
+    if (round == 0) p.iscal[I_WELL] = (nweak == 0) ? 1 : 0;
   }
-  (void)round;
 }
 
 // ------------------------------------------------------------------ apply
@@ -223,12 +236,15 @@ __device__ __forceinline__ f64x4 to_operand(f64x4 x, double* sc, int li, int kg)
 }
 
 template <typename T, int NB>
-__device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, double* scratch) {
+__device__ __forceinline__ void apply_tri(const Prob& p, int round, bool single, int tile, double* scratch) {
   const int rp = p.rpad, nb = rp / 16, ld = p.ld;
   const int wave = wave_id(), lane = threadIdx.x & 63, li = lane & 15, kg = lane >> 4;
   const int rowbase = tile * APPLY_ROWS + wave * 16;
+  // round 0 maps Y to Q1 (or, when the second round is skipped, straight to the pass operand);
+  // round 1 maps Q1 to the pass operand
+  const bool final_out = (round == 1) || single;
   const gmem<const T>* __restrict__ in = gp((const T*)((round == 0) ? p.y : p.q1));
-  gmem<T>* __restrict__ out = gp((T*)((round == 0) ? p.q1 : p.zm));
+  gmem<T>* __restrict__ out = gp((T*)(final_out ? p.zm : p.q1));
   const gmem<const double>* __restrict__ R = gp((const double*)p.H);
   const gmem<const double>* __restrict__ Dinv = gp((const double*)p.F);
   gmem<bf16>* __restrict__ zhi = gp(p.zhi);
@@ -268,7 +284,7 @@ __device__ __forceinline__ void apply_tri(const Prob& p, int round, int tile, do
         const int64_t o = (int64_t)(16 * J + li) * ld + rowbase + 4 * v + kg;
         const T val = (T)q[v];
         out[o] = val;
-        if (round == 1 && p.prec == B3) {
+        if (final_out && p.prec == B3) {
           const bf16 h = (bf16)(float)val;
           zhi[o] = h;
           zlo[o] = (bf16)((float)val - (float)h);
@@ -363,14 +379,17 @@ __device__ __forceinline__ void apply_factor(const Prob& p, int tile) {
 
 template <int NB>
 __global__ __launch_bounds__(AP_THREADS) void k_apply(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                      int nprob, int round) {
+                                                      int nprob, int arg) {
   __shared__ double scratch[AP_WAVES * 16 * 17];
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
+  const int round = arg & ORTH_ROUND_MASK;
+  const bool single = orth_single(p, arg);
+  if (round == 1 && single) return;   // the first round already wrote the pass operand
   const int t = blockIdx.x - tstart[pi];
   if (t * APPLY_ROWS >= p.ld) return;
-  if (p.prec == F64) apply_tri<double, NB>(p, round, t, scratch);
-  else apply_tri<float, NB>(p, round, t, scratch);
+  if (p.prec == F64) apply_tri<double, NB>(p, round, single, t, scratch);
+  else apply_tri<float, NB>(p, round, single, t, scratch);
 }
 
 template <int NB>

@@ -66,9 +66,11 @@ __device__ void gram_tile(const Prob& p, int mode, int tile, int chunk) {
 }
 
 __global__ __launch_bounds__(256) void k_gram(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                              int nprob, int mode) {
+                                              int nprob, int arg) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
+  const int mode = arg & ORTH_ROUND_MASK;
+  if (mode == 1 && orth_single(p, arg)) return;   // second CholeskyQR round not needed
   const int t = blockIdx.x - tstart[pi];
   const int nt = p.rpad / GRAM_TILE;
   const int ntiles = (mode == 2) ? nt * nt : nt * (nt + 1) / 2;
@@ -84,9 +86,11 @@ __global__ __launch_bounds__(256) void k_gram(const Prob* __restrict__ probs, co
 // Mode 2 symmetrises: C <- (C + C^T)/2.  A non-finite entry sets E_NONFINITE.
 constexpr int GRED_PER_BLOCK = 256;
 __global__ __launch_bounds__(256) void k_gram_reduce(const Prob* __restrict__ probs, const int* __restrict__ tstart,
-                                                     int nprob, int mode) {
+                                                     int nprob, int arg) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
+  const int mode = arg & ORTH_ROUND_MASK;
+  if (mode == 1 && orth_single(p, arg)) return;
   const int rp = p.rpad;
   const int64_t RR = (int64_t)rp * rp;
   double* dst = (mode == 2) ? p.C : p.G;

@@ -187,22 +187,24 @@ static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
     }
     add(K_ALPHA, 0, W_ALPHA, 0);
   }
-  auto orth = [&](int when, int iter) {
+  // o: position of the orthonormalisation in each problem's sequence (see orth_single)
+  auto orth = [&](int when, int iter, int o) {
+    const int a0 = 0 + 16 * (o + 1), a1 = 1 + 16 * (o + 1);
     add(K_PASS, 0, when, iter);
     add(K_PRED, 0, when, iter);
-    add(K_GRAM_SYM, 0, when, iter);
-    add(K_GRED, 0, when, iter);
-    add(K_CHOL, 0, when, iter);
-    add(K_APPLY, 0, when, iter);
-    add(K_GRAM_SYM, 1, when, iter);
-    add(K_GRED, 1, when, iter);
-    add(K_CHOL, 1, when, iter);
-    add(K_APPLY, 1, when, iter);
+    add(K_GRAM_SYM, a0, when, iter);
+    add(K_GRED, a0, when, iter);
+    add(K_CHOL, a0, when, iter);
+    add(K_APPLY, a0, when, iter);
+    add(K_GRAM_SYM, a1, when, iter);
+    add(K_GRED, a1, when, iter);
+    add(K_CHOL, a1, when, iter);
+    add(K_APPLY, a1, when, iter);
   };
-  orth(W_ALL, 0);
+  orth(W_ALL, 0, 0);
   for (int it = 0; it < max_q; ++it) {
-    orth(W_POWER, it);
-    orth(W_POWER, it);
+    orth(W_POWER, it, 1 + 2 * it);
+    orth(W_POWER, it, 2 + 2 * it);
   }
   add(K_PASS, 0, W_ALL, 0);
   add(K_PRED, 0, W_ALL, 0);

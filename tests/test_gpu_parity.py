@@ -95,6 +95,38 @@ def test_parity_ragged_padded_rows(prec, variant, alpha, n, lda):
     assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("variant,alpha", [("plain", 0.0), ("scaled", 0.0)])
+@pytest.mark.parametrize("q", [2, 3])
+def test_parity_power_steps(prec, variant, alpha, q):
+    """Several power steps (Alg. 1 with q = 2, 3): the orthonormalisations before the last one
+    only fix the range, and a well-conditioned sketch takes one CholeskyQR round there."""
+    n, k, p = 777, 40, 12
+    A, lam, U = matrix("medium", n, 5, n_pos=60)
+    proj, P, res = run_gpu(A, k, p, q, variant, prec, seed=4, alpha=alpha)
+    ref = run_oracle(A, k, p, q, variant, prec, seed=4, alpha=alpha)
+    assert res.status == 0
+    err = parity(P, ref, A)
+    print(f"{prec} {variant} q={q}: parity {err:.3e} r+ {res.r_plus}/{ref.r_plus}")
+    assert err < TOL[prec]
+    assert np.array_equal(P, P.T)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_parity_ill_conditioned_sketch(prec):
+    """Eigenvalues decaying over twelve decades: the sketch's Cholesky pivots fall far below
+    its Gram diagonal, so every orthonormalisation keeps its second CholeskyQR round."""
+    n, k, p, q = 120, 44, 8, 2
+    lam = 10.0 ** (-np.linspace(0.0, 12.0, n))
+    lam[1::3] *= -1.0
+    A, _, U = matrix("spectrum", n, 12, lam=lam)
+    for variant in ("plain", "scaled"):
+        proj, P, res = run_gpu(A, k, p, q, variant, prec, seed=6)
+        ref = run_oracle(A, k, p, q, variant, prec, seed=6)
+        assert res.status == 0
+        assert parity(P, ref, A) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_exact_recovery(prec):
     """rank(A) <= k+p: the projection is A_+ (closed form) to working precision."""
