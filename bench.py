@@ -78,8 +78,13 @@ def parse():
     ap.add_argument("--no-fp32-compare", action="store_true", help="skip timing the plain FP32 form")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-side-timings", action="store_true",
-                    help="skip the untimed single-request and sequential/grouped comparison timings "
-                         "(profiler runs: only the warmup, kernel-table and timed steps launch kernels)")
+                    help="skip the untimed single-request, one-in-flight and sequential/grouped comparison "
+                         "timings (profiler runs: only the warmup, kernel-table and timed steps launch "
+                         "kernels, all with --inflight steps in flight)")
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="steps in flight: consecutive steps go round-robin to this many HIP streams, each "
+                         "with its own workspace and outputs, so one step's latency-bound eigensolve "
+                         "overlaps the next step's streaming kernels (1: one stream)")
     ap.add_argument("--sequential", action="store_true",
                     help="time the step as two psdproj_run calls instead of one grouped psdproj_batch")
     ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "counters"],
@@ -133,35 +138,71 @@ def main() -> int:
     torch.cuda.synchronize()
     log(f"workload n={n} generated on the GPU in {time.perf_counter() - t0:.1f}s")
 
-    plain = Projector(n, k, p, q, "plain", args.precision, seed=args.seed, device=dev)
-    scaled = Projector(n, k, p, q, "scaled", args.precision, seed=args.seed, alpha=0.0,
-                       alpha_iters=args.alpha_iters, device=dev)
-    both = BatchProjector([dict(n=n, k=k, p=p, q=q, variant="plain", precision=args.precision, seed=args.seed),
-                           dict(n=n, k=k, p=p, q=q, variant="scaled", precision=args.precision, seed=args.seed,
-                                alpha=0.0, alpha_iters=args.alpha_iters)], device=dev)
-    P1 = torch.empty_like(A)
-    P2 = torch.empty_like(A)
+    inflight = max(1, args.inflight)
+    spec_plain = dict(n=n, k=k, p=p, q=q, variant="plain", precision=args.precision, seed=args.seed)
+    spec_scaled = dict(n=n, k=k, p=p, q=q, variant="scaled", precision=args.precision, seed=args.seed,
+                       alpha=0.0, alpha_iters=args.alpha_iters)
+
+    class Slot:
+        """One step's worth of projectors, workspaces and outputs, and its stream."""
+
+        def __init__(self, stream):
+            self.plain = Projector(n, k, p, q, "plain", args.precision, seed=args.seed, device=dev)
+            self.scaled = Projector(n, k, p, q, "scaled", args.precision, seed=args.seed, alpha=0.0,
+                                    alpha_iters=args.alpha_iters, device=dev)
+            self.both = BatchProjector([spec_plain, spec_scaled], device=dev)
+            self.P1 = torch.empty_like(A)
+            self.P2 = torch.empty_like(A)
+            self.stream = stream
+
+        def sequential(self):
+            self.plain(A, self.P1, stream=self.stream)
+            self.scaled(A, self.P2, stream=self.stream)
+
+        def grouped(self):
+            self.both([A, A], [self.P1, self.P2], stream=self.stream)
+
+        def results(self, sequential):
+            return (self.plain.result(), self.scaled.result()) if sequential else tuple(self.both.results())
+
+    # slot 0 runs on the current stream; further slots on streams of their own
+    slots = [Slot(None)] + [Slot(torch.cuda.Stream(device=dev)) for _ in range(inflight - 1)]
+    plain, scaled, both = slots[0].plain, slots[0].scaled, slots[0].both
+    P1, P2 = slots[0].P1, slots[0].P2
 
     def step_sequential():
-        plain(A, P1)
-        scaled(A, P2)
+        slots[0].sequential()
 
     def step_grouped():
-        both([A, A], [P1, P2])
+        slots[0].grouped()
 
     step = step_sequential if args.sequential else step_grouped
-    for _ in range(args.warmup):
-        step()
+
+    def run_steps(count, nflight):
+        """`count` steps, step i on slot i mod nflight; returns once all are enqueued."""
+        if nflight > 1:
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(dev))
+            for sl in slots[1:nflight]:
+                sl.stream.wait_event(ev)
+        for i in range(count):
+            sl = slots[i % nflight]
+            sl.sequential() if args.sequential else sl.grouped()
+
+    run_steps(max(args.warmup, inflight), inflight)
     torch.cuda.synchronize()
-    r1, r2 = (plain.result(), scaled.result()) if args.sequential else tuple(both.results())
-    if r1.status or r2.status:
-        log(f"device status plain={r1.status} scaled={r2.status}")
-        return 1
+    for sl in slots:
+        ra, rb = sl.results(args.sequential)
+        if ra.status or rb.status:
+            log(f"device status plain={ra.status} scaled={rb.status}")
+            return 1
+    r1, r2 = slots[0].results(args.sequential)
 
     # ---------------------------------------------------------------- per-kernel device times
-    # Every launch bracketed by HIP events, over `args.steps` untimed steps: the kernel table,
-    # and which kernel dominates.  (Two event records per launch lengthen a step of ~90 short
-    # launches by several per cent, so the timed region below times the dominant kernel only.)
+    # Every launch bracketed by HIP events, over `args.steps` untimed steps run like the timed
+    # ones (`inflight` in flight): the kernel table, and which kernel dominates.  (Two event
+    # records per launch lengthen a step of ~90 short launches by several per cent, so the
+    # timed region below times the dominant kernel only.)
     def read_profile():
         out = {}
         for kind in range(pp.psdproj_kernel_kinds()):
@@ -174,28 +215,43 @@ def main() -> int:
     pp.psdproj_profile_select(None)
     pp.psdproj_profile_reset()
     pp.psdproj_profile_enable(True)
-    for _ in range(args.steps):
-        step()
+    run_steps(args.steps, inflight)
     torch.cuda.synchronize()
     pp.psdproj_profile_enable(False)
     kern = read_profile()
     dom = max(kern, key=lambda kname: kern[kname]["total_ms"])
 
     # ---------------------------------------------------------------- timed region
-    # HIP events around the dominant kernel's launches only (on the library's stream)
+    # `inflight` steps in flight; HIP events (on the stream of each launch) around the dominant
+    # kernel's launches only
     pp.psdproj_profile_select([kern[dom]["kind"]])
     pp.psdproj_profile_reset()
     pp.psdproj_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    run_steps(args.steps, inflight)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     pp.psdproj_profile_enable(False)
     pp.psdproj_profile_select(None)
     dom_timed = read_profile()[dom]
     ms_per_step = 1e3 * elapsed / args.steps
+
+    # the same steps one at a time on one stream (per-step time without overlap), the dominant
+    # kernel timed the same way (a side timing: skipped with --no-side-timings)
+    ms_one, dom_one = None, None
+    if inflight > 1 and not args.no_side_timings:
+        pp.psdproj_profile_select([kern[dom]["kind"]])
+        pp.psdproj_profile_reset()
+        pp.psdproj_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(args.steps, 1)
+        torch.cuda.synchronize()
+        ms_one = 1e3 * (time.perf_counter() - t0) / args.steps
+        pp.psdproj_profile_enable(False)
+        pp.psdproj_profile_select(None)
+        dom_one = read_profile()[dom]
     value = 2.0 * args.steps / elapsed
     log(f"{args.steps} steps in {elapsed:.3f}s: {ms_per_step:.3f} ms/step, {value:.1f} projections/s")
 
@@ -271,7 +327,13 @@ def main() -> int:
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 ("algorithmic_flops_per_launch" if unit == "TFLOP/s" else "algorithmic_bytes_per_launch"): alg,
                 "problems_per_launch": round(units / launches_per_step, 3),
-                "avg_launch_us": round(d["avg_us"], 2), "model": note}
+                "avg_launch_us": round(d["avg_us"], 2), "model": note,
+                "timed_with": f"{inflight} step(s) in flight" + (
+                    ": the kernel's launches overlap the other step's kernels" if inflight > 1 else "")}
+    if dom_one is not None:
+        ach1 = alg / (dom_one["avg_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
+        roofline["one_in_flight"] = {"avg_launch_us": round(dom_one["avg_us"], 2), "achieved": round(ach1, 1),
+                                     "frac": round(ach1 / peak, 4)}
 
     # every A-streaming kernel against the HBM roofline (algorithmic bytes per launch).  A pass
     # launch reads A once whether it covers one problem or the two problems of the step, which
@@ -298,13 +360,16 @@ def main() -> int:
         "config": {"workload": f"large_20k: n={n}, k={k}, p={p}, q={q}; one plain (Alg. 2) + one scaled (Alg. 3, "
                                f"alpha by Alg. 5 with N={args.alpha_iters}) projection per step; A fp32 resident",
                    "n": n, "k": k, "p": p, "q": q, "precision": args.precision,
-                   "step": "two psdproj_run calls" if args.sequential else "one grouped psdproj_batch of both"},
+                   "step": "two psdproj_run calls" if args.sequential else "one grouped psdproj_batch of both",
+                   "inflight": inflight},
+        "ms_per_step_one_in_flight": rnd(ms_one, 4) if inflight > 1 else round(ms_per_step, 4),
         "ms_per_step_" + ("grouped" if args.sequential else "sequential"): rnd(ms_other, 4),
         "tflops": round(tflops, 2), "hbm_gbs": round(gbs, 1),
         "latency_ms": {"plain": rnd(ms_plain, 3), "scaled": rnd(ms_scaled, 3)},
         "r_plus": {"plain": r1.r_plus, "scaled": r2.r_plus}, "alpha": r2.alpha_used,
         "roofline": roofline,
         "a_streaming": streaming,
+        "kernels_timed_with": f"{inflight} step(s) in flight",
         "kernels": {kname: {"avg_us": round(v["avg_us"], 2), "launches_per_step": v["launches"] / args.steps,
                             "ms_per_step": round(v["total_ms"] / args.steps, 4)} for kname, v in kern.items()},
     }
