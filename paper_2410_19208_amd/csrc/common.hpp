@@ -71,7 +71,7 @@ struct Prob {
   const void* A; int64_t lda;
   void* P; int64_t ldp;
   // workspace pointers
-  void* zm; bf16* zhi; bf16* zlo;  // pass operand: master (double/float) and BF16 split
+  void* zm; bf16* zhi; bf16* zlo;  // pass operand: master (double/float) and BF16 split (tiled)
   void* y;                         // reduced pass output
   void* part;                      // split-K partials
   void* q1;                        // first-round CholQR panel
@@ -87,6 +87,16 @@ struct Prob {
   int32_t* drop;                   // rpad flags
   psdproj_result* res;
 };
+
+// Element (row i, column j) of the BF16 split copies of the pass operand (ld rows x rpad
+// columns).  They are stored in 1 KB tiles of 32 rows x 16 columns, tile (i/32, j/16) at
+// (j/16 * ld/32 + i/32) x 512 elements, and inside a tile chunk-major: rows 8c .. 8c+7 of
+// column jj (one 16-byte chunk) at 128 c + 8 jj.  One K step of the pass then loads each
+// column block as one contiguous 1 KB piece, straight into the LDS order its MFMA operand
+// reads take without bank conflicts.
+__host__ __device__ __forceinline__ int64_t zsplit_index(int i, int j, int ld) {
+  return ((int64_t)(j >> 4) * (ld >> 5) + (i >> 5)) * 512 + ((i >> 3) & 3) * 128 + (j & 15) * 8 + (i & 7);
+}
 
 __device__ __forceinline__ bool orth_single(const Prob& p, int arg) {
   const int o = (arg >> 4) - 1;

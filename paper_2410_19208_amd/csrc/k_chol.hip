@@ -286,8 +286,9 @@ __device__ __forceinline__ void apply_tri(const Prob& p, int round, bool single,
         out[o] = val;
         if (final_out && p.prec == B3) {
           const bf16 h = (bf16)(float)val;
-          zhi[o] = h;
-          zlo[o] = (bf16)((float)val - (float)h);
+          const int64_t oz = zsplit_index(rowbase + 4 * v + kg, 16 * J + li, ld);
+          zhi[oz] = h;
+          zlo[oz] = (bf16)((float)val - (float)h);
         }
       }
     }

@@ -303,10 +303,11 @@ __host__ __device__ constexpr int pb_lds_bytes(int ncb) { return PB_RING * pb_sl
 __host__ __device__ constexpr int pb_zpw(int ncb) { return (2 * ncb + 7) / 8; }
 
 // Z slice layout: block b (1 KB) holds columns 16cb .. 16cb+15 of hi (b = cb) or lo
-// (b = NCB + cb), 64 bytes (32 K values) per column; slot s of column j holds the K chunk
-// s ^ pb_swz(j).  The swizzle gives distinct bank groups to every 8 and every 16 consecutive
-// lanes of an operand read (lane (li, kg) reads chunk kg of column li).
-__device__ __forceinline__ int pb_swz(int j) { return ((j >> 1) ^ (j >> 3)) & 3; }
+// (b = NCB + cb) for the step's 32 K rows, copied whole from one tile of the split panel
+// (zsplit_index): chunk c (K rows 8c .. 8c+7) of column jj at byte 256 c + 16 jj.  Lane (li, kg)
+// of an MFMA operand read takes chunk kg of column li, byte 16 x lane: 64 consecutive 16-byte
+// pieces, which a ds_read_b128 serves without bank conflicts (64 bytes per column instead,
+// swizzled or not, costs about 1.6x as long per read).
 
 // s_waitcnt with vmcnt = N (0..63), lgkmcnt = 0, expcnt unchanged
 #define PB_VMCNT(N) (0x0070 | ((N) & 15) | (((N) >> 4) << 14))
@@ -368,14 +369,14 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
       }
     }
     unsigned char* zs = smem + S * SB;
-    const int j = lane >> 2;
-    const int c = (lane & 3) ^ pb_swz(j);
 #pragma unroll
     for (int u = 0; u < ZPW; ++u) {
       const int b = (wave + NW * u) % (2 * NCB);
       const gmem<const bf16>* z = (b < NCB) ? zhi : zlo;
       const int cb = (b < NCB) ? b : b - NCB;
-      dma16((const void*)(z + (int64_t)(cb * 16 + j) * ld + k0 + 8 * c), zs + b * 1024);
+      // tile (k0 / 32, cb) of the split panel starts at element (cb ld / 32 + k0 / 32) 512, which
+      // is cb 16 ld + 16 k0 as k0 is a multiple of 32
+      dma16((const void*)(z + (int64_t)cb * 16 * ld + 16 * k0 + 8 * lane), zs + b * 1024);
     }
   };
 
@@ -388,7 +389,7 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
     __asm__ volatile("s_barrier" ::: "memory");
   };
 
-  const int zoff = li * 64 + ((kg ^ pb_swz(li)) << 4);
+  const int zoff = lane << 4;   // chunk kg of column li
   auto compute = [&](auto S_, int st) {
     constexpr int S = decltype(S_)::value;
     const int kvalid = kend - (kbeg + st * PB_BK);

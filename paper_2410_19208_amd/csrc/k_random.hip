@@ -71,7 +71,10 @@ __global__ __launch_bounds__(256) void k_omega(const Prob* __restrict__ probs, c
     } else {
       float f = (float)v;
       ((float*)p.zm)[idx] = f;
-      if (p.prec == B3) split_bf16(f, p.zhi[idx], p.zlo[idx]);
+      if (p.prec == B3) {
+        const int64_t oz = zsplit_index(i, j, p.ld);
+        split_bf16(f, p.zhi[oz], p.zlo[oz]);
+      }
     }
   }
 }
