@@ -135,6 +135,12 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// Raw buffer resources (stride 0): an access at or past num_records bytes reads zero and writes
+// nothing.  Fourth descriptor word of the gfx9 family (32-bit data format), and the cache-policy
+// bit that marks a buffer access non-temporal.
+constexpr int BUF_WORD3 = 0x00020000;
+constexpr int BUF_NT = 2;
+
 // 16 bytes per lane from global memory into LDS at dst + 16 * lane (dst wave-uniform), without
 // a VGPR round trip (global_load_lds_dwordx4); complete after this wave's vmcnt reaches 0.
 __device__ __forceinline__ void dma16(const void* g, unsigned char* dst) {

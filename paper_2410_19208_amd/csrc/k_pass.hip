@@ -351,19 +351,32 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[v][cb] = f32x4{0, 0, 0, 0};
 
+  // 16-byte path: A read as a raw buffer whose range starts at row k0 of the step and ends at the
+  // last element of row n - 1, so a row at or past n reads as zero without a per-lane clamp, and
+  // every load is one scalar base plus this lane's fixed offset (row 8kg, column mcol) plus e rows.
+  const int64_t lda4 = lda * 4;
+  const uint32_t voff = (uint32_t)(((int64_t)8 * kg * lda + mcol) * 4);
+
   // loads of step st into ring slot S.  Steps past the last one load the last step again (a
-  // slot nobody reads), and rows at or past the chunk end read row kbeg (zeroed at use), so
-  // every step issues the same loads and the compiler's wait counts stay exact.
+  // slot nobody reads), and rows at or past the chunk end are zeroed at use (the element path
+  // reads row kbeg for them), so every step issues the same loads and the compiler's wait
+  // counts stay exact.
   auto issue = [&](auto S_, int st) {
     constexpr int S = decltype(S_)::value;
     const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
+    if constexpr (AVEC) {
+      const int64_t left = ((int64_t)(n - 1 - k0) * lda + n) * 4;   // bytes from row k0 to A's end
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)((const float*)p.A + (int64_t)k0 * lda), 0, (int)(uint32_t)min(left, (int64_t)0xffffffff),
+          BUF_WORD3);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + 8 * kg + e;
-      const int64_t row = (int64_t)((k < kend) ? k : kbeg) * lda;
-      if constexpr (AVEC) {
-        ar[S][e] = __builtin_nontemporal_load((const gmem<VT>*)(A + row + mcol));
-      } else {
+      for (int e = 0; e < 8; ++e)
+        ar[S][e] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, (int)(e * lda4), BUF_NT));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + 8 * kg + e;
+        const int64_t row = (int64_t)((k < kend) ? k : kbeg) * lda;
 #pragma unroll
         for (int q = 0; q < VB; ++q) ar[S][e][q] = A[row + min(mc + q, n - 1)];
       }
