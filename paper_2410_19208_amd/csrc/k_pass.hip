@@ -296,6 +296,7 @@ constexpr int PB_VB = 2;
 constexpr int PB_BK = 32;
 constexpr int PB_DIST = 2;                       // steps in flight ahead of the one computed
 constexpr int PB_RING = PB_DIST + 1;
+static_assert(PASS_BK_F % PB_BK == 0, "K chunks must be whole pass steps");
 __host__ __device__ constexpr int pb_slice_bytes(int ncb) { return ncb * 2048; }   // hi + lo
 __host__ __device__ constexpr int pb_lds_bytes(int ncb) { return PB_RING * pb_slice_bytes(ncb); }
 // Z blocks (1 KB) per wave and step: wave w issues blocks w, w + 8, ... mod 2 ncb, so every
@@ -400,6 +401,9 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   auto wait_step = [&]() {
     __builtin_amdgcn_s_waitcnt(PB_VMCNT(LPS));
     __asm__ volatile("s_barrier" ::: "memory");
+    // nothing that uses the step's A registers may be scheduled above the wait (the wait
+    // analysis would then drain every load in flight)
+    __builtin_amdgcn_sched_barrier(0);
   };
 
   const int zoff = lane << 4;   // chunk kg of column li
@@ -412,7 +416,9 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         float x = ar[S][e][v];
-        if (kvalid < PB_BK && 8 * kg + e >= kvalid) x = 0.0f;
+        // rows past the chunk end: on the 16-byte path the only partial step is the last one of
+        // A (chunks are whole steps), whose rows past n the buffer range already read as zero
+        if (!AVEC && kvalid < PB_BK && 8 * kg + e >= kvalid) x = 0.0f;
         const bf16 hb = (bf16)x;
         ahi[v][e] = hb;
         alo[v][e] = (bf16)(x - (float)hb);
