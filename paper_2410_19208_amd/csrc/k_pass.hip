@@ -407,10 +407,13 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   };
 
   const int zoff = lane << 4;   // chunk kg of column li
-  auto compute = [&](auto S_, int st) {
+  // hi/lo split of the A values of ring slot S (step st), done (up to width 14) one step ahead,
+  // half-way through the previous step, so that its VALU work runs beside that step's MFMAs
+  // instead of holding back the first MFMA of its own step
+  bf16x8 ahi[PB_RING][VB], alo[PB_RING][VB];
+  auto split = [&](auto S_, int st) {
     constexpr int S = decltype(S_)::value;
     const int kvalid = kend - (kbeg + st * PB_BK);
-    bf16x8 ahi[VB], alo[VB];
 #pragma unroll
     for (int v = 0; v < VB; ++v)
 #pragma unroll
@@ -420,46 +423,69 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
         // A (chunks are whole steps), whose rows past n the buffer range already read as zero
         if (!AVEC && kvalid < PB_BK && 8 * kg + e >= kvalid) x = 0.0f;
         const bf16 hb = (bf16)x;
-        ahi[v][e] = hb;
-        alo[v][e] = (bf16)(x - (float)hb);
+        ahi[S][v][e] = hb;
+        alo[S][v][e] = (bf16)(x - (float)hb);
       }
-    // widths 12 and 16: split before any MFMA of the step (interleaving the two runs out of
-    // registers there); elsewhere the interleaved schedule fits and is faster
-    if constexpr (NCB == 12 || NCB == 16) __builtin_amdgcn_sched_barrier(0);
+  };
+
+  // MFMAs of column-block pairs [cb0, cb1) of the step in ring slot S: 2 VB independent
+  // accumulators between dependent MFMAs
+  auto mfmas = [&](auto S_, auto CB0_, auto CB1_) {
+    constexpr int S = decltype(S_)::value;
     const unsigned char* zs = smem + S * SB;
-    // column blocks in pairs: 2 VB independent accumulators between dependent MFMAs
 #pragma unroll
-    for (int cb = 0; cb < NCB; cb += 2) {
+    for (int cb = decltype(CB0_)::value; cb < decltype(CB1_)::value; cb += 2) {
       const bf16x8 h0 = *(const bf16x8*)(zs + cb * 1024 + zoff);
       const bf16x8 h1 = *(const bf16x8*)(zs + (cb + 1) * 1024 + zoff);
       const bf16x8 l0 = *(const bf16x8*)(zs + (NCB + cb) * 1024 + zoff);
       const bf16x8 l1 = *(const bf16x8*)(zs + (NCB + cb + 1) * 1024 + zoff);
 #pragma unroll
       for (int v = 0; v < VB; ++v) {
-        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], h0, acc[v][cb], 0, 0, 0);
-        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], h1, acc[v][cb + 1], 0, 0, 0);
+        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[S][v], h0, acc[v][cb], 0, 0, 0);
+        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[S][v], h1, acc[v][cb + 1], 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < VB; ++v) {
-        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], l0, acc[v][cb], 0, 0, 0);
-        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[v], l1, acc[v][cb + 1], 0, 0, 0);
+        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[S][v], l0, acc[v][cb], 0, 0, 0);
+        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[S][v], l1, acc[v][cb + 1], 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < VB; ++v) {
-        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[v], h0, acc[v][cb], 0, 0, 0);
-        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[v], h1, acc[v][cb + 1], 0, 0, 0);
+        acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[S][v], h0, acc[v][cb], 0, 0, 0);
+        acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[S][v], h1, acc[v][cb + 1], 0, 0, 0);
       }
     }
   };
 
+  // this wave's A loads of the step after the current one have landed: the only loads issued
+  // after them are that step's Z slices and the loads of the step after it.  The scheduling
+  // barrier keeps the split below the wait (a use hoisted above it would make the wait
+  // analysis drain every load in flight).
+  auto wait_next_a = [&]() {
+    __builtin_amdgcn_s_waitcnt(PB_VMCNT(AVEC ? LPS + ZPW : 0));
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
   // one step in ring slot S (= st mod PB_RING): its loads landed everywhere (the barrier also
   // ends every wave's reads of step st - 1, whose slot step st + PB_DIST overwrites), issue
-  // step st + PB_DIST, compute step st
+  // step st + PB_DIST, compute step st, and half-way through split the A of step st + 1
+  // (widths above 14 have no registers for two split steps: they split at the start of the step)
+  constexpr bool AHEAD = NCB <= 14;
+  constexpr int HALF = 2 * ((NCB / 2 + 1) / 2);   // column blocks before the split
   auto step = [&](auto S_, int st) {
     constexpr int S = decltype(S_)::value;
     wait_step();
     issue(std::integral_constant<int, (S + PB_DIST) % PB_RING>{}, st + PB_DIST);
-    compute(S_, st);
+    if constexpr (AHEAD) {
+      mfmas(S_, std::integral_constant<int, 0>{}, std::integral_constant<int, HALF>{});
+      wait_next_a();
+      split(std::integral_constant<int, (S + 1) % PB_RING>{}, st + 1);
+      mfmas(S_, std::integral_constant<int, HALF>{}, std::integral_constant<int, NCB>{});
+    } else {
+      split(S_, st);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(S_, std::integral_constant<int, 0>{}, std::integral_constant<int, NCB>{});
+    }
   };
 
   using S0 = std::integral_constant<int, 0>;
@@ -468,6 +494,10 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   static_assert(PB_RING == 3, "the step loop below is unrolled for a ring of three");
   issue(S0{}, 0);
   issue(S1{}, 1);
+  if constexpr (AHEAD) {
+    wait_next_a();
+    split(S0{}, 0);
+  }
   int st = 0;
   for (; st + 3 <= nsteps; st += 3) {
     step(S0{}, st);
