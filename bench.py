@@ -199,10 +199,12 @@ def main() -> int:
     r1, r2 = slots[0].results(args.sequential)
 
     # ---------------------------------------------------------------- per-kernel device times
-    # Every launch bracketed by HIP events, over `args.steps` untimed steps run like the timed
-    # ones (`inflight` in flight): the kernel table, and which kernel dominates.  (Two event
-    # records per launch lengthen a step of ~90 short launches by several per cent, so the
-    # timed region below times the dominant kernel only.)
+    # Every launch bracketed by HIP events, over `args.steps` untimed steps run one at a time:
+    # the kernel table, and which kernel dominates (the most device time of its own per step;
+    # with steps overlapping, a launch's duration also counts the time it shares the GPU with
+    # the other step, which favours the many short launches).  (Two event records per launch
+    # lengthen a step of ~90 short launches by several per cent, so the timed region below
+    # times the dominant kernel only.)
     def read_profile():
         out = {}
         for kind in range(pp.psdproj_kernel_kinds()):
@@ -215,7 +217,7 @@ def main() -> int:
     pp.psdproj_profile_select(None)
     pp.psdproj_profile_reset()
     pp.psdproj_profile_enable(True)
-    run_steps(args.steps, inflight)
+    run_steps(args.steps, 1)
     torch.cuda.synchronize()
     pp.psdproj_profile_enable(False)
     kern = read_profile()
@@ -290,7 +292,7 @@ def main() -> int:
     tflops = (flops_plain + flops_scaled) / step_s / 1e12
     gbs = (bytes_plain + bytes_scaled) / step_s / 1e9
 
-    # roofline of the dominant kernel (largest device time per step), with its launches timed
+    # roofline of the dominant kernel (largest device time per step, one step at a time), with its launches timed
     # in the timed region.  A grouped launch covers every problem active in its stage, so the
     # algorithmic work of one launch is the per-problem figure times the problem-launches of
     # the step over its launches.
@@ -369,7 +371,7 @@ def main() -> int:
         "r_plus": {"plain": r1.r_plus, "scaled": r2.r_plus}, "alpha": r2.alpha_used,
         "roofline": roofline,
         "a_streaming": streaming,
-        "kernels_timed_with": f"{inflight} step(s) in flight",
+        "kernels_timed_with": "1 step in flight",
         "kernels": {kname: {"avg_us": round(v["avg_us"], 2), "launches_per_step": v["launches"] / args.steps,
                             "ms_per_step": round(v["total_ms"] / args.steps, 4)} for kname, v in kern.items()},
     }
