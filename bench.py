@@ -81,7 +81,7 @@ def parse():
                     help="skip the untimed single-request, one-in-flight and sequential/grouped comparison "
                          "timings (profiler runs: only the warmup, kernel-table and timed steps launch "
                          "kernels, all with --inflight steps in flight)")
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="steps in flight: consecutive steps go round-robin to this many HIP streams, each "
                          "with its own workspace and outputs, so one step's latency-bound eigensolve "
                          "overlaps the next step's streaming kernels (1: one stream)")
@@ -197,6 +197,10 @@ def main() -> int:
             log(f"device status plain={ra.status} scaled={rb.status}")
             return 1
     r1, r2 = slots[0].results(args.sequential)
+    # every slot computed the same two projections of the same A: their outputs agree bit for bit
+    slots_equal = all(torch.equal(sl.P1, slots[0].P1) and torch.equal(sl.P2, slots[0].P2) for sl in slots[1:])
+    if not slots_equal:
+        log("outputs of the in-flight slots differ")
 
     # ---------------------------------------------------------------- per-kernel device times
     # Every launch bracketed by HIP events, over `args.steps` untimed steps run one at a time:
@@ -331,7 +335,7 @@ def main() -> int:
                 "problems_per_launch": round(units / launches_per_step, 3),
                 "avg_launch_us": round(d["avg_us"], 2), "model": note,
                 "timed_with": f"{inflight} step(s) in flight" + (
-                    ": the kernel's launches overlap the other step's kernels" if inflight > 1 else "")}
+                    ": the kernel's launches overlap the other steps' kernels" if inflight > 1 else "")}
     if dom_one is not None:
         ach1 = alg / (dom_one["avg_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
         roofline["one_in_flight"] = {"avg_launch_us": round(dom_one["avg_us"], 2), "achieved": round(ach1, 1),
@@ -364,6 +368,7 @@ def main() -> int:
                    "n": n, "k": k, "p": p, "q": q, "precision": args.precision,
                    "step": "two psdproj_run calls" if args.sequential else "one grouped psdproj_batch of both",
                    "inflight": inflight},
+        "slots_bitwise_equal": slots_equal,
         "ms_per_step_one_in_flight": rnd(ms_one, 4) if inflight > 1 else round(ms_per_step, 4),
         "ms_per_step_" + ("grouped" if args.sequential else "sequential"): rnd(ms_other, 4),
         "tflops": round(tflops, 2), "hbm_gbs": round(gbs, 1),
