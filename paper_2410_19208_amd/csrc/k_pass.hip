@@ -359,9 +359,10 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   const uint32_t voff = (uint32_t)(((int64_t)8 * kg * lda + mcol) * 4);
 
   // loads of step st into ring slot S.  Steps past the last one load the last step again (a
-  // slot nobody reads), and rows at or past the chunk end are zeroed at use (the element path
-  // reads row kbeg for them), so every step issues the same loads and the compiler's wait
-  // counts stay exact.
+  // slot nobody reads), so every step issues the same loads and the compiler's wait counts stay
+  // exact.  Rows at or past the chunk end: on the 16-byte path a chunk ends on a step boundary
+  // unless it ends at n, and rows past n read as zero; the element path reads row kbeg for them
+  // and zeroes them at use.
   auto issue = [&](auto S_, int st) {
     constexpr int S = decltype(S_)::value;
     const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
