@@ -35,7 +35,7 @@
  *
  * Errors
  *   Argument errors are returned synchronously and nothing is enqueued.  Errors found on
- *   the device (non-finite input, alpha <= 0, breakdown) are written to
+ *   the device (non-finite input, estimated alpha <= 0) are written to
  *   result_dev->status after the stream completes; P is then unspecified.  No exception
  *   or abort crosses the ABI.
  *
@@ -69,7 +69,11 @@ typedef enum {
     PSDPROJ_E_INVALID = 1,     /* bad argument (synchronous) */
     PSDPROJ_E_ALPHA = 2,       /* scaled: estimated alpha <= 0 or not finite (device) */
     PSDPROJ_E_NONFINITE = 3,   /* NaN/Inf met in a Gram or compressed matrix (device) */
-    PSDPROJ_E_BREAKDOWN = 4,   /* orthonormalisation lost every direction (device) */
+    PSDPROJ_E_BREAKDOWN = 4,   /* reserved, never returned: a sketch column that the
+                                  orthonormalisation finds dependent is dropped (a zero column
+                                  of Q), which leaves range(Q) = range(Y) exact, and a sketch
+                                  with no independent column is Y = 0, whose projection P = 0
+                                  is the correct result (Alg. 1, Alg. 2) */
     PSDPROJ_E_NOMEM = 5,       /* workspace too small or host allocation failed */
     PSDPROJ_E_BUDGET = 6,      /* server: request larger than the HBM budget */
     PSDPROJ_E_DEVICE = 7,      /* a HIP runtime call failed */
@@ -158,7 +162,9 @@ psdproj_status psdproj_batch(int32_t count, const psdproj_plan_t* plans, const v
  * projections, each one Alg. 1 + Alg. 2 or Alg. 3).  hbm_budget_bytes of device memory is
  * allocated at creation and holds the workspaces of the requests in flight.  Requests are
  * admitted in FIFO order while their workspaces fit in it and fewer than max_inflight are in
- * flight; each admission round becomes one grouped launch sequence (as psdproj_batch) on one
+ * flight.  The budget covers only the memory the server itself allocates: A and P are
+ * caller-owned buffers that exist before submit and stay allocated whether or not a request
+ * is admitted, so admitting or deferring a request changes nothing in their footprint; each admission round becomes one grouped launch sequence (as psdproj_batch) on one
  * of two server streams, and arrivals join at the next round.  A and P stay caller-owned and
  * must stay valid until the ticket completes.  Each request's P is bitwise identical to a
  * psdproj_run of the same desc.  submit validates synchronously (E_INVALID; E_BUDGET when the

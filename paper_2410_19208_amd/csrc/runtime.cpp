@@ -563,7 +563,7 @@ const char* psdproj_status_str(psdproj_status s) {
     case PSDPROJ_E_INVALID: return "invalid argument";
     case PSDPROJ_E_ALPHA: return "estimated alpha is not positive and finite";
     case PSDPROJ_E_NONFINITE: return "non-finite value in a Gram or compressed matrix";
-    case PSDPROJ_E_BREAKDOWN: return "orthonormalisation lost every direction";
+    case PSDPROJ_E_BREAKDOWN: return "reserved (never returned)";
     case PSDPROJ_E_NOMEM: return "workspace too small or allocation failed";
     case PSDPROJ_E_BUDGET: return "request exceeds the server HBM budget";
     case PSDPROJ_E_DEVICE: return "HIP runtime error";
