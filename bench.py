@@ -8,7 +8,11 @@ k = 200, p = 20, q = 1.  One step = one plain projection (Alg. 2) and one scaled
 projection (Alg. 3 with alpha estimated by Alg. 5, N = 10) of the same resident matrix,
 run as one grouped launch sequence through the C ABI (psdproj_batch) with the split-BF16
 (bf16x3) MFMA passes; the same two projections one after the other (psdproj_run each) are
-timed beside it.
+timed beside it.  After the timed region (none of it counts towards `value`): the plain FP32
+form of the same projections (latency, and parity with the oracle), a short serving leg
+(Poisson arrivals at 200 and 1000 requests/s through the continuous-batching server, p50/p99
+latency, against the FP32 form one request at a time), and the FP64 oracle (parity and the
+host-core baseline).  The exit status is 1 when a parity check exceeds its tolerance.
 
 Prints one JSON line (see the repository's design notes for the field definitions).
 """
@@ -30,6 +34,8 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+# relative Frobenius distance to the FP64 oracle on the same inputs
+PARITY_TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large_20k_bf16x3.md")
@@ -93,7 +99,8 @@ def parse():
                          "counters: a short run for hardware-counter profiles (symmetric Gaussian A, no QR "
                          "in the generator, two grouped steps, then one 1 GiB device copy for calibration)")
     ap.add_argument("--qps", default="50,100,200,500,1000,2000", help="serve mode: arrival rates")
-    ap.add_argument("--serve-requests", type=int, default=400, help="serve mode: requests per rate (at most)")
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="requests per arrival rate (at most) in serve mode and in the serving leg of the step")
     return ap.parse_args()
 
 
@@ -308,17 +315,14 @@ def main() -> int:
         units = 2 * (args.alpha_iters + 1)
         note = "upper triangle of the symmetric A read once per product plus two FP64 vectors"
     elif dom == "k_pass":
-        # Matrix-core bound: the problems of a grouped launch that stream the same A share its
-        # reads in L2 (tile pairing), so HBM is not the binding resource.  Algorithmic flops per
-        # problem-pass: the products the precision's scheme needs, 2 n^2 r each (BF16x3: the
-        # three BF16 products hi*hi, hi*lo, lo*hi).
-        nprod, peak = {"bf16x3": (3, BF16_PEAK_TFLOPS), "fp32": (1, FP32_PEAK_TFLOPS),
-                       "fp64": (1, FP64_PEAK_TFLOPS)}[args.precision]
-        bound, unit = "mfma", "TFLOP/s"
-        per_unit = nprod * 2 * nn * r
+        # Algorithmic bytes: one read of A per problem-pass, n^2 s (the problems of a grouped
+        # launch that stream the same A share its reads in L2, so the launch moves fewer bytes
+        # than it is credited with).  The matrix-core work the precision's scheme issues is
+        # reported beside it (BF16x3: three BF16 products of 2 n^2 r flops per problem-pass).
+        per_unit = nn * es
         units = 2 * passes
-        note = (f"{nprod} matrix-core product(s) of 2 n^2 r flops per pass and problem, "
-                f"r = k + p = {r}; {args.precision} peak")
+        note = (f"one read of A (n^2 x {es} bytes) per pass and problem; a grouped launch covers both "
+                f"problems of the step")
     elif dom == "k_rebuild":
         per_unit = nn * es
         units = 2
@@ -336,27 +340,36 @@ def main() -> int:
                 "avg_launch_us": round(d["avg_us"], 2), "model": note,
                 "timed_with": f"{inflight} step(s) in flight" + (
                     ": the kernel's launches overlap the other steps' kernels" if inflight > 1 else "")}
+    if dom == "k_pass":
+        nprod, mpeak = {"bf16x3": (3, BF16_PEAK_TFLOPS), "fp32": (1, FP32_PEAK_TFLOPS),
+                        "fp64": (1, FP64_PEAK_TFLOPS)}[args.precision]
+        fl = nprod * 2 * nn * r * units / launches_per_step
+        tf = fl / (d["avg_us"] * 1e-6) / 1e12
+        roofline["mfma_issued"] = {"flops_per_launch": fl, "achieved": round(tf, 1), "peak": mpeak,
+                                   "unit": "TFLOP/s", "frac": round(tf / mpeak, 4),
+                                   "model": f"{nprod} matrix-core product(s) of 2 n^2 r flops per pass and "
+                                            f"problem, r = k + p = {r}"}
     if dom_one is not None:
         ach1 = alg / (dom_one["avg_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
         roofline["one_in_flight"] = {"avg_launch_us": round(dom_one["avg_us"], 2), "achieved": round(ach1, 1),
                                      "frac": round(ach1 / peak, 4)}
 
-    # every A-streaming kernel against the HBM roofline (algorithmic bytes per launch).  A pass
-    # launch reads A once whether it covers one problem or the two problems of the step, which
-    # stream the same A and share its reads.
+    # every A-streaming kernel against the HBM roofline (algorithmic bytes per launch: a pass is
+    # credited with one read of A per problem it covers, although the two problems of the step
+    # share their reads of A in L2).
     streaming = {}
-    for kname, per_launch, per_problem, problems_step in (
-            ("k_pass", nn * es, None, 2 * passes),
-            ("k_gemv", None, n * (n + 1) / 2 * es + 2 * n * 8.0, 2 * (args.alpha_iters + 1)),
-            ("k_rebuild", None, nn * es, 2)):
+    for kname, per_problem, problems_step in (
+            ("k_pass", nn * es, 2 * passes),
+            ("k_gemv", n * (n + 1) / 2 * es + 2 * n * 8.0, 2 * (args.alpha_iters + 1)),
+            ("k_rebuild", nn * es, 2)):
         if kname in kern:
             kd = kern[kname]
             lps = kd["launches"] / args.steps
             ppl = problems_step / lps
-            b = per_launch if per_launch is not None else per_problem * ppl
-            gbs = b / (kd["avg_us"] * 1e-6) / 1e9
+            b = per_problem * ppl
+            kgbs = b / (kd["avg_us"] * 1e-6) / 1e9
             streaming[kname] = {"gb_per_launch": round(b / 1e9, 4), "avg_us": round(kd["avg_us"], 2),
-                                "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                                "achieved_gbs": round(kgbs, 1), "frac_hbm": round(kgbs / HBM_PEAK_GBS, 4),
                                 "traffic_bytes": measured_traffic(kname, ppl)}
 
     out = {
@@ -382,6 +395,9 @@ def main() -> int:
     }
 
     # ---------------------------------------------------------------- FP32 single-request comparison
+    # the plain FP32 form of the same two projections, one request at a time; its outputs are kept
+    # for the parity check against the oracle below
+    Pf = None
     if not args.no_fp32_compare and not args.no_side_timings and args.precision == "bf16x3":
         f1 = Projector(n, k, p, q, "plain", "fp32", seed=args.seed, device=dev)
         f2 = Projector(n, k, p, q, "scaled", "fp32", seed=args.seed, alpha=0.0, alpha_iters=args.alpha_iters,
@@ -389,11 +405,37 @@ def main() -> int:
         f1(A, P1)
         f2(A, P2)
         out["fp32_latency_ms"] = {"plain": round(one(f1, P1, 3), 3), "scaled": round(one(f2, P2, 3), 3)}
+        Pf = {"plain": f1(A, torch.empty_like(A)), "scaled": f2(A, torch.empty_like(A))}
+        torch.cuda.synchronize()
+        if f1.result().status or f2.result().status:
+            log("FP32 comparison run reported a device error")
+            return 1
         del f1, f2
         plain(A, P1)
         scaled(A, P2)
 
+    # ---------------------------------------------------------------- serving leg
+    # Poisson arrivals through the request server, requests drawn from a pool of leading
+    # principal blocks of the resident matrix (symmetric, of the same spectral character),
+    # against the plain FP32 form one request at a time at the same arrivals
+    if not args.no_side_timings and args.precision == "bf16x3":
+        buckets = [b for b in (256, 512, 1024, 2048, 4096, 8192, 16384) if b <= n]
+        pool = {b: A[:b, :b] for b in buckets}
+        serve_points(pool, buckets, [50.0], 40, "bf16x3", 64, dev, 99)   # warm-up
+        out["serving"] = {
+            "workload": "Poisson arrivals; n log-uniform in [256, 16384] snapped to log-spaced buckets, k in "
+                        "{20,50,100,200}, p=10, q=1, plain/scaled 50/50 (alpha by Alg. 5, N=10); requests read "
+                        "leading principal blocks of the resident matrix; latency = finish - submit",
+            "bf16x3_continuous_batching": serve_points(pool, buckets, [200.0, 1000.0], args.serve_requests,
+                                                       "bf16x3", 64, dev, 7000),
+            "fp32_one_at_a_time": serve_points(pool, buckets, [200.0, 1000.0], args.serve_requests, "fp32", 1,
+                                               dev, 7000)}
+        if any(pt["errors"] for v in out["serving"].values() if isinstance(v, list) for pt in v):
+            log("serving leg reported device errors")
+            return 1
+
     # ---------------------------------------------------------------- oracle: parity and CPU baseline
+    parity_ok = True
     if not args.no_cpu_baseline:
         from oracle import rnla
         try:
@@ -421,16 +463,26 @@ def main() -> int:
                                "sample": f"{reps} x (one plain + one scaled projection) of the same n={n} workload "
                                          f"(full FP64 oracle incl. Alg. 5 and the n x n rebuild), {cpu_s:.1f} s"}
         a_fro = float(np.linalg.norm(A_host))
+        tol = PARITY_TOL[args.precision]
         par = {}
         for name, Pd, o in (("plain", P1, o1), ("scaled", P2, o2)):
             Ph = Pd.cpu().numpy().astype(np.float64)
             par[name] = rnla.parity_error(Ph, o.P, a_fro)
             del Ph
-        tol = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 5e-5}[args.precision]
         out["parity"] = {"plain": par["plain"], "scaled": par["scaled"], "tol": tol,
                          "metric": "||P-P_oracle||_F / max(||P_oracle||_F, 1e-2 ||A||_F)",
                          "alpha_oracle": o2.alpha, "r_plus_oracle": {"plain": o1.r_plus, "scaled": o2.r_plus}}
+        parity_ok = max(par.values()) < tol
+        if Pf is not None:
+            pf = {}
+            for name, o in (("plain", o1), ("scaled", o2)):
+                Ph = Pf[name].cpu().numpy().astype(np.float64)
+                pf[name] = rnla.parity_error(Ph, o.P, a_fro)
+                del Ph
+            out["parity_fp32"] = {"plain": pf["plain"], "scaled": pf["scaled"], "tol": PARITY_TOL["fp32"]}
+            parity_ok = parity_ok and max(pf.values()) < PARITY_TOL["fp32"]
         del A_host, o1, o2
+    Pf = None
     # accuracy against the exact projection (closed form from the generator's spectrum)
     lam_pos = torch.as_tensor(lam[pos], device=dev)
     Apos = (Upos * lam_pos[None, :]) @ Upos.T
@@ -440,6 +492,9 @@ def main() -> int:
     out["e_alg"] = ea
     del Apos
     print(json.dumps(out), flush=True)
+    if not parity_ok:
+        log("parity against the oracle exceeds the tolerance")
+        return 1
     return 0
 
 
@@ -531,35 +586,23 @@ def run_batch(args, dev) -> int:
     return 0 if (same == 256 and bad == 0) else 1
 
 
-def run_serve(args, dev) -> int:
-    """Poisson arrivals through the request server: n from a device-resident pool of seven
-    size buckets (256 .. 16384, log-spaced: a log-uniform draw is snapped to the nearest
-    bucket), k uniform in {20, 50, 100, 200}, p = 10, q = 1, variant 50/50 (scaled with alpha
-    from Alg. 5, N = 10), BF16x3; latency = finish - submit per request."""
+def serve_points(pool, buckets, qps_list, max_requests, precision, max_inflight, dev, seed0):
+    """One serving measurement per arrival rate: Poisson arrivals (workloads.serving_requests),
+    each request's n snapped to the nearest pool bucket (log scale), submitted to a fresh server
+    (16 GiB budget, `max_inflight` requests in flight; 1 = the plain one-at-a-time FIFO form).
+    Latency = finish - submit per request (host clock of the server)."""
     import numpy as np
-    import torch
 
     import workloads
     from paper_2410_19208_amd.torch_api import Server
 
-    buckets = [256, 512, 1024, 2048, 4096, 8192, 16384]
-    t0 = time.perf_counter()
-    pool = {}
-    for n in buckets:
-        U = workloads.haar_orthogonal(n, 5000 + n, device="cuda")
-        lam = workloads.spectrum_large(n, 0.05, 5000 + n)
-        pool[n] = workloads.from_spectrum(U, lam).to(torch.float32).contiguous()
-        del U
-    torch.cuda.synchronize()
-    log(f"serving pool generated in {time.perf_counter() - t0:.1f}s")
-
     def snap(n):
         return min(buckets, key=lambda b: abs(math.log(b) - math.log(n)))
 
-    def run_point(qps, max_inflight, seed, precision=None):
-        precision = precision or args.precision
-        count = min(args.serve_requests, max(20, int(qps * 3)))
-        reqs = workloads.serving_requests(count, qps, seed)
+    out = []
+    for i, qps in enumerate(qps_list):
+        count = min(max_requests, max(20, int(qps * 3)))
+        reqs = workloads.serving_requests(count, qps, seed0 + i)
         srv = Server(16 << 30, max_inflight, device=dev)
         tickets = []
         start = time.perf_counter()
@@ -582,15 +625,37 @@ def run_serve(args, dev) -> int:
         srv.close()
         lat = np.array(lat) * 1e3
         span = max(fin) - min(sub)
-        return {"qps": qps, "requests": count, "achieved_rps": round(count / span, 1),
-                "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-                "errors": errs}
+        out.append({"qps": qps, "requests": count, "achieved_rps": round(count / span, 1),
+                    "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 2), "errors": errs})
+        log(f"serve {precision} inflight<={max_inflight} at {qps:g} req/s: {out[-1]}")
+    return out
 
-    # warm-up: compile/initialise on a few requests
-    run_point(50, 64, 99)
-    points = [run_point(float(x), 64, 7000 + i) for i, x in enumerate(args.qps.split(","))]
+
+def run_serve(args, dev) -> int:
+    """Poisson arrivals through the request server: n from a device-resident pool of seven
+    size buckets (256 .. 16384, log-spaced: a log-uniform draw is snapped to the nearest
+    bucket), k uniform in {20, 50, 100, 200}, p = 10, q = 1, variant 50/50 (scaled with alpha
+    from Alg. 5, N = 10), BF16x3; latency = finish - submit per request."""
+    import torch
+
+    import workloads
+
+    buckets = [256, 512, 1024, 2048, 4096, 8192, 16384]
+    t0 = time.perf_counter()
+    pool = {}
+    for n in buckets:
+        U = workloads.haar_orthogonal(n, 5000 + n, device="cuda")
+        lam = workloads.spectrum_large(n, 0.05, 5000 + n)
+        pool[n] = workloads.from_spectrum(U, lam).to(torch.float32).contiguous()
+        del U
+    torch.cuda.synchronize()
+    log(f"serving pool generated in {time.perf_counter() - t0:.1f}s")
+    qps = [float(x) for x in args.qps.split(",")]
+    serve_points(pool, buckets, [50.0], 40, args.precision, 64, dev, 99)   # warm-up
+    points = serve_points(pool, buckets, qps, args.serve_requests, args.precision, 64, dev, 7000)
     # the plain FP32 form one request at a time (FIFO, nothing overlapped), same arrivals
-    base = [run_point(float(x), 1, 7000 + i, "fp32") for i, x in enumerate(args.qps.split(",")[:4])]
+    base = serve_points(pool, buckets, qps[:4], args.serve_requests, "fp32", 1, dev, 7000)
     out = {"metric": "PSD projection serving: throughput and p50/p99 latency at Poisson QPS",
            "value": max(pt["achieved_rps"] for pt in points), "unit": "requests/s (max achieved)", "n_gpus": 1,
            "higher_is_better": True, "dtype": args.precision, "data": "synthetic",

@@ -66,6 +66,8 @@ struct Prob {
   int32_t ngchunk, alpha_iters;    // Gram row chunks, N of Alg. 4/5
   int32_t alpha_mode, rwpad;       // 0: alpha given (or plain), 1: estimate; rebuild-factor row stride
   int32_t npass_tiles, avec;       // avec: rows of A start and end 16-byte aligned (vector loads)
+  int32_t ktail, pad0;             // BF16X3 16-byte path: K rows ktail .. n-1 (n mod 32 of them)
+                                   // are added by the pass reduction, not the pass (else n)
   uint64_t seed;
   double alpha_in;
   const void* A; int64_t lda;

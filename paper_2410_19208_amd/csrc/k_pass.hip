@@ -332,7 +332,9 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   const int m0 = (t / p.split) * PASS_BM_F;
   const int n = p.n, ld = p.ld;
   const int kbeg = s * p.kchunk;
-  const int kend = min(n, kbeg + p.kchunk);
+  // 16-byte path: whole steps only (rows from ktail, n rounded down to a multiple of the step,
+  // up to n are added by k_pass_reduce)
+  const int kend = max(kbeg, min(AVEC ? p.ktail : n, kbeg + p.kchunk));
   const int nsteps = (kend - kbeg + PB_BK - 1) / PB_BK;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int li = lane & 15, kg = lane >> 4;
@@ -360,9 +362,9 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
 
   // loads of step st into ring slot S.  Steps past the last one load the last step again (a
   // slot nobody reads), so every step issues the same loads and the compiler's wait counts stay
-  // exact.  Rows at or past the chunk end: on the 16-byte path a chunk ends on a step boundary
-  // unless it ends at n, and rows past n read as zero; the element path reads row kbeg for them
-  // and zeroes them at use.
+  // exact.  Rows at or past the chunk end: the 16-byte path has none (its chunks are whole steps
+  // and stop before ktail, so every row it reads is below n); the element path reads row kbeg
+  // for them and zeroes them at use.
   auto issue = [&](auto S_, int st) {
     constexpr int S = decltype(S_)::value;
     const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
@@ -420,8 +422,7 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         float x = ar[S][e][v];
-        // rows past the chunk end: on the 16-byte path the only partial step is the last one of
-        // A (chunks are whole steps), whose rows past n the buffer range already read as zero
+        // rows past the chunk end (element path only: the 16-byte path has whole steps)
         if (!AVEC && kvalid < PB_BK && 8 * kg + e >= kvalid) x = 0.0f;
         const bf16 hb = (bf16)x;
         ahi[S][v][e] = hb;
@@ -493,6 +494,8 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   using S1 = std::integral_constant<int, 1>;
   using S2 = std::integral_constant<int, 2>;
   static_assert(PB_RING == 3, "the step loop below is unrolled for a ring of three");
+  // a chunk that ktail leaves empty (nsteps = 0, kbeg >= 64 as n >= 32 on the 16-byte path)
+  // loads the step before it, whose rows are below n, and writes a zero partial tile
   issue(S0{}, 0);
   issue(S1{}, 1);
   if constexpr (AHEAD) {
@@ -577,6 +580,14 @@ __device__ __forceinline__ void reduce_body(const Prob& p, int64_t vbase) {
     V v = {};
     if (col < p.r && row < p.n) {
       for (int s = 0; s < split; ++s) v += *(const gmem<V>*)(part + (int64_t)s * P + idx);
+      if constexpr (sizeof(T) == 4) {
+        // rows ktail .. n-1 of the K range, which the 16-byte BF16X3 pass leaves out (fewer
+        // than 32): FP32 products added in K order, A[k][row .. row+VW-1] read as one vector (A
+        // is symmetric; rows of A are 16-byte aligned and n % 4 == 0 on that path)
+        const gmem<const T>* __restrict__ A = gp((const T*)p.A);
+        for (int k = p.ktail; k < p.n; ++k)
+          v += *(const gmem<V>*)(A + (int64_t)k * p.lda + row) * z[(int64_t)col * p.ld + k];
+      }
       if (scaled) v = (v + alpha * *(const gmem<V>*)(z + idx)) / alpha;
 #pragma unroll
       for (int q = 0; q < VW; ++q)

@@ -116,6 +116,10 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   // 16-byte loads of A: rows start 16-byte aligned and end on a 16-byte boundary, so an
   // aligned 16-byte chunk of a row lies wholly inside or wholly past column n
   p.avec = ((lda * pl.es) % 16 == 0 && (d.n * pl.es) % 16 == 0) ? 1 : 0;
+  // the 16-byte BF16X3 pass reads whole 32-row steps of A, all below n; the partial step's rows
+  // are added by the pass reduction (n < 32: the element path)
+  if (pl.prec == B3 && d.n < 32) p.avec = 0;
+  p.ktail = (pl.prec == B3 && p.avec) ? (int)(d.n - d.n % 32) : (int)d.n;
   auto at = [&](size_t off) { return (void*)(region + off); };
   p.zm = at(pl.o_zm);
   p.zhi = (bf16*)(pl.prec == B3 ? at(pl.o_zhi) : nullptr);

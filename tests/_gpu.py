@@ -6,7 +6,7 @@ import pytest
 import workloads
 from oracle import rnla
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 5e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
 
 
 def device():

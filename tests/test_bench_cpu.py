@@ -53,3 +53,8 @@ def test_committed_summary_parses():
     for kernel, ppl in (("k_pass", 2.0), ("k_gemv", 1.0), ("k_rebuild", 2.0)):
         v = bench.measured_traffic(kernel, ppl)
         assert v is None or v > 0
+
+
+def test_parity_tolerances():
+    # the split-BF16 form is held to the FP32 bar: the same stated accuracy
+    assert bench.PARITY_TOL == {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
