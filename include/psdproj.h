@@ -158,6 +158,28 @@ psdproj_status psdproj_batch(int32_t count, const psdproj_plan_t* plans, const v
                              const int64_t* lda, void* const* P, const int64_t* ldp, void* workspace,
                              size_t workspace_bytes, psdproj_result* results_dev, psdproj_stream_t stream);
 
+/* The launch sequence of a run or batch captured once as a HIP graph and replayed.  A grouped
+ * sequence reaches its problems only through the descriptor header at the start of the
+ * workspace, so psdproj_run, psdproj_batch and the server replay a captured sequence whenever a
+ * run has the same schedule (plans, grouping) and the same workspace address as an earlier one;
+ * the header is rewritten before each replay (a sequence is captured the second time it is
+ * seen, at most 64 are kept; PSDPROJ_GRAPHS=0 in the environment launches every kernel
+ * directly, and so does a run while kernel timing is enabled).  psdproj_graph_stats reports how
+ * many sequences were captured and replayed that way.
+ * psdproj_graph_create captures the batch given (arguments as psdproj_batch) into a graph that
+ * owns nothing but its launches: it writes the header into the workspace now (synchronously) and
+ * every psdproj_graph_launch replays the whole sequence on `stream` against the same A, P,
+ * workspace and results, which must stay valid, and the workspace unused by anything else, until
+ * psdproj_graph_destroy.  A may change between launches.  Each replay gives bitwise the P of
+ * psdproj_batch on the same inputs. */
+typedef struct psdproj_graph_s* psdproj_graph_t;
+psdproj_status psdproj_graph_create(int32_t count, const psdproj_plan_t* plans, const void* const* A,
+                                    const int64_t* lda, void* const* P, const int64_t* ldp, void* workspace,
+                                    size_t workspace_bytes, psdproj_result* results_dev, psdproj_graph_t* out);
+psdproj_status psdproj_graph_launch(psdproj_graph_t graph, psdproj_stream_t stream);
+void           psdproj_graph_destroy(psdproj_graph_t graph);
+psdproj_status psdproj_graph_stats(int64_t* captures, int64_t* replays);
+
 /* Continuous-batching request server on the current device (the batching of many independent
  * projections, each one Alg. 1 + Alg. 2 or Alg. 3).  hbm_budget_bytes of device memory is
  * allocated at creation and holds the workspaces of the requests in flight.  Requests are
@@ -190,6 +212,15 @@ psdproj_status psdproj_philox_words(uint64_t seed, uint32_t stream_id, uint64_t 
 /* Elements start .. start+count-1 of a Gaussian stream, as double. */
 psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count,
                                 double* out_dev, psdproj_stream_t stream);
+
+/* Tile shapes.  The split-K factor of the passes over A (the number of K chunks whose partial
+ * products are summed in a fixed order) comes from a table keyed by precision, n bucket
+ * (2^b <= n < 2^(b+1), b clamped to 6..14) and padded width r_pad, written by the tuner that
+ * times every candidate on the GPU (paper_2410_19208_amd/tune.py); outside the table a built-in
+ * rule applies.  psdproj_tile_override(precision, split) makes plans created afterwards with that
+ * precision use split (1..16; 0 restores the table), for the tuner's measurements.  A plan keeps
+ * the factor it was created with, so a problem gets the same P alone, batched or served. */
+psdproj_status psdproj_tile_override(int32_t precision, int32_t split);
 
 /* Kernel timing (tracing aid, off by default).  While enabled, every launch of the library
  * is bracketed by HIP events recorded on the launch stream; psdproj_profile_read waits for

@@ -14,7 +14,8 @@ import os
 __all__ = [
     "PLAIN", "SCALED", "FP64", "FP32", "BF16X3", "Desc", "Result", "Layout", "PsdprojError",
     "lib", "psdproj_plan", "psdproj_plan_destroy", "psdproj_plan_layout", "psdproj_run",
-    "psdproj_batch_workspace", "psdproj_batch", "psdproj_server_create", "psdproj_submit",
+    "psdproj_batch_workspace", "psdproj_batch", "psdproj_graph_create", "psdproj_graph_launch",
+    "psdproj_graph_destroy", "psdproj_graph_stats", "psdproj_tile_override", "psdproj_server_create", "psdproj_submit",
     "psdproj_poll", "psdproj_wait", "psdproj_server_times", "psdproj_server_destroy",
     "psdproj_philox_words", "psdproj_gaussian", "psdproj_status_str", "psdproj_abi_version",
     "EXPORTED", "LIB_PATH",
@@ -74,6 +75,12 @@ _SIGS = {
     "psdproj_batch_workspace": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_sz)]),
     "psdproj_batch": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64),
                              ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp, _vp]),
+    "psdproj_graph_create": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64),
+                                    ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp, ctypes.POINTER(_vp)]),
+    "psdproj_graph_launch": (_i32, [_vp, _vp]),
+    "psdproj_graph_destroy": (None, [_vp]),
+    "psdproj_graph_stats": (_i32, [ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "psdproj_tile_override": (_i32, [_i32, _i32]),
     "psdproj_server_create": (_i32, [_sz, _i32, ctypes.POINTER(_vp)]),
     "psdproj_submit": (_i32, [_vp, ctypes.POINTER(Desc), _vp, _i64, _vp, _i64, ctypes.POINTER(_u64)]),
     "psdproj_poll": (_i32, [_vp, _u64, ctypes.POINTER(Result)]),
@@ -180,6 +187,36 @@ def psdproj_batch(plans, A, lda, P, ldp, workspace, workspace_bytes, results_dev
     m = len(plans)
     _check(lib.psdproj_batch(m, (_vp * m)(*plans), (_vp * m)(*A), (_i64 * m)(*lda), (_vp * m)(*P),
                              (_i64 * m)(*ldp), workspace, workspace_bytes, results_dev, stream), "psdproj_batch")
+
+
+def psdproj_graph_create(plans, A, lda, P, ldp, workspace, workspace_bytes, results_dev):
+    """Capture the batch (arguments as psdproj_batch) into a replayable HIP graph handle."""
+    m = len(plans)
+    h = _vp()
+    _check(lib.psdproj_graph_create(m, (_vp * m)(*plans), (_vp * m)(*A), (_i64 * m)(*lda), (_vp * m)(*P),
+                                    (_i64 * m)(*ldp), workspace, workspace_bytes, results_dev, ctypes.byref(h)),
+           "psdproj_graph_create")
+    return h.value
+
+
+def psdproj_graph_launch(graph, stream=0) -> None:
+    _check(lib.psdproj_graph_launch(graph, stream), "psdproj_graph_launch")
+
+
+def psdproj_graph_destroy(graph) -> None:
+    lib.psdproj_graph_destroy(graph)
+
+
+def psdproj_graph_stats():
+    """(sequences captured, replays) of the run/batch/server graph cache."""
+    c, r = _i64(), _i64()
+    _check(lib.psdproj_graph_stats(ctypes.byref(c), ctypes.byref(r)), "psdproj_graph_stats")
+    return c.value, r.value
+
+
+def psdproj_tile_override(precision, split) -> None:
+    """Plans created afterwards with `precision` use pass split-K `split` (0: the tuned table)."""
+    _check(lib.psdproj_tile_override(int(precision), int(split)), "psdproj_tile_override")
 
 
 def psdproj_server_create(hbm_budget_bytes, max_inflight):

@@ -41,6 +41,7 @@ constexpr int GRAM_CHUNK = 1024;              // rows per Gram partial
 constexpr int RB_TILE = 128;                  // rebuild output tile (P)
 constexpr int APPLY_ROWS = 64;                // rows per apply/formw tile
 constexpr int GEMV_TILE = 256;                // GEMV tile edge (upper-triangle tiles of A)
+constexpr int MAX_SPLIT = 16;               // pass split-K factors 1 .. MAX_SPLIT
 constexpr int NSCAL = 16;
 constexpr int NISCAL = 16;
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -16,6 +17,38 @@ namespace psd {
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------------------ tile table
+// Split-K of the passes per (precision, n bucket, padded width), chosen by the tuner
+// (paper_2410_19208_amd/tune.py, which times every candidate on the GPU and writes
+// tile_table.inc).  Bucket b holds 2^b <= n < 2^(b+1) (b clamped to [6, 14]); a missing entry
+// keeps the built-in rule.  An override (psdproj_tile_override) takes precedence, for the tuner's
+// own measurements.
+namespace {
+struct TileEntry { int prec, nlog2, rpad, split; };
+const TileEntry TILE_TABLE[] = {
+#include "tile_table.inc"
+};
+std::mutex tile_mu;
+int tile_override[3] = {0, 0, 0};
+
+int n_bucket(int64_t n) {
+  int b = 0;
+  while (b < 62 && (int64_t(1) << (b + 1)) <= n) ++b;
+  return std::min(14, std::max(6, b));
+}
+
+int tuned_split(int prec, int64_t n, int rpad) {
+  {
+    std::lock_guard<std::mutex> g(tile_mu);
+    if (tile_override[prec] > 0) return tile_override[prec];
+  }
+  const int b = n_bucket(n);
+  for (const TileEntry& e : TILE_TABLE)
+    if (e.prec == prec && e.nlog2 == b && e.rpad == rpad) return e.split;
+  return 0;
+}
+}  // namespace
 
 // ------------------------------------------------------------------------------ planning
 psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
@@ -53,6 +86,8 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   const int mt = (n + bm - 1) / bm;
   int split = (pl.prec == F64) ? std::min(8, std::max(1, (512 + mt - 1) / mt))
                                : std::min(8, std::max(1, (n + 63) / 64));
+  const int tuned = tuned_split(pl.prec, n, pl.rpad);
+  if (tuned > 0) split = std::min(tuned, MAX_SPLIT);
   int kchunk = rup((n + split - 1) / split, bk);
   split = (n + kchunk - 1) / kchunk;
   pl.split = split;
@@ -94,11 +129,10 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.o_iscal = take(NISCAL * 4);
   pl.o_drop = take(PSDPROJ_MAX_RANK * 4);
   pl.region = o;
-  // header for a single run
-  Schedule s;
+  // schedule and header of a single run
   const Plan* one = &pl;
-  build_schedule(&one, 1, s);
-  pl.header_single = s.header_bytes;
+  build_schedule(&one, 1, pl.single);
+  pl.header_single = pl.single.header_bytes;
   return PSDPROJ_OK;
 }
 
@@ -369,7 +403,7 @@ Prof& prof() { static Prof P; return P; }
 }  // namespace
 
 // Enqueue every launch of a schedule whose header (Prob array + tile tables) is at `hdr`.
-psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream) {
+psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream, bool allow_timing) {
   kernel_init_once();
   const Prob* probs = (const Prob*)hdr;
   const int* tdev = (const int*)(hdr + s.prob_bytes);
@@ -377,7 +411,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
   std::unique_lock<std::mutex> plock(PR.mu, std::defer_lock);
   bool timing_on = false;
   uint64_t timed_kinds = 0;
-  {
+  if (allow_timing) {
     std::lock_guard<std::mutex> g(PR.mu);
     timing_on = PR.on;
     timed_kinds = PR.kinds;
@@ -429,6 +463,146 @@ static const char* const KIND_NAMES[K_NKINDS] = {
     "k_gram_full", "k_gram_reduce", "k_chol", "k_apply", "k_tridiag", "k_bisect", "k_invit", "k_rebuild",
     "k_finalize", "k_gemv_finish", "k_apply_factor", "k_backxf"};
 
+// ------------------------------------------------------------------------------ HIP graphs
+// A schedule's launches reach the problems only through the header at `hdr` (each kernel
+// takes a pointer to its problems' descriptors and tile table there), so one captured launch
+// sequence serves every run with the same schedule and the same header address, whatever A, P
+// and the results are: the header is rewritten before each replay.  The sequence holds kernel
+// nodes only.
+psdproj_status capture_schedule(const Schedule& s, unsigned char* hdr, hipGraph_t* graph, hipGraphExec_t* exec) {
+  *graph = nullptr;
+  *exec = nullptr;
+  kernel_init_once();   // function attributes are set before the capture, not inside it
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return PSDPROJ_E_DEVICE;
+  psdproj_status st = PSDPROJ_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipStreamDestroy(cs);
+    return PSDPROJ_E_DEVICE;
+  }
+  st = enqueue(s, hdr, cs, /*allow_timing=*/false);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  hipStreamDestroy(cs);
+  if (st != PSDPROJ_OK || e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    return PSDPROJ_E_DEVICE;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x) {
+    hipGraphDestroy(g);
+    return PSDPROJ_E_DEVICE;
+  }
+  *graph = g;
+  *exec = x;
+  return PSDPROJ_OK;
+}
+
+namespace {
+// Captured sequences of the runs issued through run_group (psdproj_run, psdproj_batch, the
+// server), keyed by (device, header address, launch list).  A key is captured the second time it
+// is seen, so one-off batches pay no instantiation; at most GRAPH_CACHE entries per process, the
+// least recently used one evicted after its last replay has completed.
+constexpr size_t GRAPH_CACHE = 64;
+struct CachedGraph {
+  std::vector<int64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;   // recorded after the latest replay
+  uint64_t last = 0;
+  int seen = 0;
+};
+struct GraphCache {
+  std::mutex mu;
+  std::vector<CachedGraph> entries;
+  uint64_t clock = 0;
+  int mode = -1;               // -1: not read yet; 0: off (PSDPROJ_GRAPHS=0); 1: on
+  int64_t replays = 0, captures = 0;
+};
+GraphCache& graph_cache() { static GraphCache C; return C; }
+
+std::vector<int64_t> schedule_key(const Schedule& s, const unsigned char* hdr) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::vector<int64_t> k;
+  k.reserve(4 + 9 * s.launches.size());
+  k.push_back(dev);
+  k.push_back((int64_t)(uintptr_t)hdr);
+  k.push_back((int64_t)s.prob_bytes);
+  k.push_back((int64_t)s.launches.size());
+  for (const LaunchRec& R : s.launches) {
+    k.push_back(R.kind); k.push_back(R.arg); k.push_back(R.first); k.push_back(R.count); k.push_back(R.prec);
+    k.push_back(R.ncb); k.push_back(R.toff); k.push_back(R.maxnb); k.push_back(R.grid);
+  }
+  return k;
+}
+
+void drop_entry(CachedGraph& e) {
+  if (e.done) { hipEventSynchronize(e.done); hipEventDestroy(e.done); }
+  if (e.exec) hipGraphExecDestroy(e.exec);
+  if (e.graph) hipGraphDestroy(e.graph);
+  e = CachedGraph();
+}
+}  // namespace
+
+// Enqueue a schedule whose header is already at `hdr`: a replay of its captured sequence when
+// there is one, otherwise the launches themselves (and a capture on the key's second run).
+// Kernel timing, when enabled, needs the launches themselves.
+psdproj_status launch_schedule(const Schedule& s, unsigned char* hdr, hipStream_t stream) {
+  GraphCache& C = graph_cache();
+  bool timing = false;
+  {
+    Prof& PR = prof();
+    std::lock_guard<std::mutex> g(PR.mu);
+    timing = PR.on;
+  }
+  std::unique_lock<std::mutex> lk(C.mu);
+  if (C.mode < 0) {
+    const char* env = std::getenv("PSDPROJ_GRAPHS");
+    C.mode = (env && env[0] == '0') ? 0 : 1;
+  }
+  if (C.mode == 0 || timing || s.launches.empty()) {
+    lk.unlock();
+    return enqueue(s, hdr, stream);
+  }
+  const std::vector<int64_t> key = schedule_key(s, hdr);
+  CachedGraph* hit = nullptr;
+  for (auto& e : C.entries)
+    if (e.key == key) { hit = &e; break; }
+  if (!hit) {
+    if (C.entries.size() >= GRAPH_CACHE) {
+      auto lru = std::min_element(C.entries.begin(), C.entries.end(),
+                                  [](const CachedGraph& a, const CachedGraph& b) { return a.last < b.last; });
+      drop_entry(*lru);
+      *lru = C.entries.back();
+      C.entries.pop_back();
+    }
+    C.entries.push_back(CachedGraph());
+    hit = &C.entries.back();
+    hit->key = key;
+  }
+  hit->last = ++C.clock;
+  hit->seen += 1;
+  if (!hit->exec && hit->seen >= 2) {
+    if (capture_schedule(s, hdr, &hit->graph, &hit->exec) == PSDPROJ_OK &&
+        hipEventCreateWithFlags(&hit->done, hipEventDisableTiming) == hipSuccess) {
+      C.captures += 1;
+    } else {
+      drop_entry(*hit);
+      hit->key = key;
+      hit->seen = -1000000;   // never captured again; launched directly
+    }
+  }
+  if (!hit->exec) {
+    lk.unlock();
+    return enqueue(s, hdr, stream);
+  }
+  if (hipGraphLaunch(hit->exec, stream) != hipSuccess) return PSDPROJ_E_DEVICE;
+  if (hipEventRecord(hit->done, stream) != hipSuccess) return PSDPROJ_E_DEVICE;
+  C.replays += 1;
+  return PSDPROJ_OK;
+}
+
 psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp) {
   const int64_t n = pl.d.n;
   if (!A || !P) return PSDPROJ_E_INVALID;
@@ -441,15 +615,14 @@ psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const 
   return PSDPROJ_OK;
 }
 
-psdproj_status run_group(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
-                         void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
-                         psdproj_result* results, hipStream_t stream) {
-  Schedule s;
+psdproj_status make_header(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
+                           void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
+                           psdproj_result* results, Schedule& s, std::vector<unsigned char>& host) {
   build_schedule(plans, count, s);
   size_t need = s.header_bytes;
   for (int i = 0; i < count; ++i) need += plans[i]->region;
   if (ws_bytes < need) return PSDPROJ_E_NOMEM;
-  std::vector<unsigned char> host(s.header_bytes, 0);
+  host.assign(s.header_bytes, 0);
   Prob* hp = (Prob*)host.data();
   // regions follow the header in the caller's order
   std::vector<size_t> roff(count);
@@ -460,9 +633,19 @@ psdproj_status run_group(int count, const Plan* const* plans, const void* const*
     hp[k] = make_prob(*plans[i], ws + roff[i], A[i], lda[i], P[i], ldp[i], results + i);
   }
   std::memcpy(host.data() + s.prob_bytes, s.tdata.data(), s.tdata.size() * sizeof(int));
-  psdproj_status st = upload(ws, host.data(), s.header_bytes, stream);
+  return PSDPROJ_OK;
+}
+
+psdproj_status run_group(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
+                         void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
+                         psdproj_result* results, hipStream_t stream) {
+  Schedule s;
+  std::vector<unsigned char> host;
+  psdproj_status st = make_header(count, plans, A, lda, P, ldp, ws, ws_bytes, results, s, host);
   if (st != PSDPROJ_OK) return st;
-  return enqueue(s, ws, stream);
+  st = upload(ws, host.data(), s.header_bytes, stream);
+  if (st != PSDPROJ_OK) return st;
+  return launch_schedule(s, ws, stream);
 }
 
 }  // namespace psd
@@ -545,6 +728,69 @@ psdproj_status psdproj_batch(int32_t count, const psdproj_plan_t* plans, const v
   }
   return run_group(count, pls.data(), A, lda, P, ldp, (unsigned char*)workspace, workspace_bytes, results_dev,
                    (hipStream_t)stream);
+}
+
+struct psdproj_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+psdproj_status psdproj_graph_create(int32_t count, const psdproj_plan_t* plans, const void* const* A,
+                                    const int64_t* lda, void* const* P, const int64_t* ldp, void* workspace,
+                                    size_t workspace_bytes, psdproj_result* results_dev, psdproj_graph_t* out) {
+  if (!out) return PSDPROJ_E_INVALID;
+  *out = nullptr;
+  if (count < 1 || !plans || !A || !lda || !P || !ldp || !workspace || !results_dev) return PSDPROJ_E_INVALID;
+  if ((uintptr_t)workspace & 255) return PSDPROJ_E_INVALID;
+  std::vector<const Plan*> pls(count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return PSDPROJ_E_INVALID;
+    pls[i] = (const Plan*)plans[i];
+    psdproj_status st = check_operands(*pls[i], A[i], lda[i], P[i], ldp[i]);
+    if (st != PSDPROJ_OK) return st;
+  }
+  Schedule s;
+  std::vector<unsigned char> host;
+  unsigned char* ws = (unsigned char*)workspace;
+  psdproj_status st = make_header(count, pls.data(), A, lda, P, ldp, ws, workspace_bytes, results_dev, s, host);
+  if (st != PSDPROJ_OK) return st;
+  // the header is written once, now; the captured sequence only reads it
+  if (hipMemcpy(ws, host.data(), s.header_bytes, hipMemcpyHostToDevice) != hipSuccess) return PSDPROJ_E_DEVICE;
+  psdproj_graph_s* g = new (std::nothrow) psdproj_graph_s();
+  if (!g) return PSDPROJ_E_NOMEM;
+  st = capture_schedule(s, ws, &g->graph, &g->exec);
+  if (st != PSDPROJ_OK) { delete g; return st; }
+  *out = g;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_graph_launch(psdproj_graph_t graph, psdproj_stream_t stream) {
+  if (!graph || !graph->exec) return PSDPROJ_E_INVALID;
+  return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? PSDPROJ_OK : PSDPROJ_E_DEVICE;
+}
+
+void psdproj_graph_destroy(psdproj_graph_t graph) {
+  if (!graph) return;
+  if (graph->exec) hipGraphExecDestroy(graph->exec);
+  if (graph->graph) hipGraphDestroy(graph->graph);
+  delete graph;
+}
+
+psdproj_status psdproj_tile_override(int32_t precision, int32_t split) {
+  if (precision < PSDPROJ_FP64 || precision > PSDPROJ_BF16X3 || split < 0 || split > MAX_SPLIT)
+    return PSDPROJ_E_INVALID;
+  std::lock_guard<std::mutex> g(tile_mu);
+  tile_override[precision] = split;
+  return PSDPROJ_OK;
+}
+
+psdproj_status psdproj_graph_stats(int64_t* captures, int64_t* replays) {
+  if (!captures || !replays) return PSDPROJ_E_INVALID;
+  GraphCache& C = graph_cache();
+  std::lock_guard<std::mutex> g(C.mu);
+  *captures = C.captures;
+  *replays = C.replays;
+  return PSDPROJ_OK;
 }
 
 psdproj_status psdproj_philox_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count, uint32_t* out_dev,
