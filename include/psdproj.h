@@ -63,6 +63,7 @@ extern "C" {
 
 #define PSDPROJ_ABI_VERSION 1
 #define PSDPROJ_MAX_RANK 256   /* k + p limit of this build */
+#define PSDPROJ_STATIC_SCRATCH_BYTES (64u << 20)   /* workspace of psdproj_run_static, per device */
 
 typedef enum {
     PSDPROJ_OK = 0,
@@ -78,7 +79,9 @@ typedef enum {
     PSDPROJ_E_BUDGET = 6,      /* server: request larger than the HBM budget */
     PSDPROJ_E_DEVICE = 7,      /* a HIP runtime call failed */
     PSDPROJ_E_PENDING = 8,     /* server: ticket not finished yet */
-    PSDPROJ_E_TIMEOUT = 9      /* server: wait timed out */
+    PSDPROJ_E_TIMEOUT = 9,     /* server: wait timed out */
+    PSDPROJ_E_SCRATCH = 10     /* psdproj_run_static: the problem's workspace exceeds the static
+                                  scratch array (synchronous) */
 } psdproj_status;
 
 typedef enum { PSDPROJ_PLAIN = 0 /* Alg. 2 */, PSDPROJ_SCALED = 1 /* Alg. 3 */ } psdproj_variant;
@@ -147,6 +150,21 @@ psdproj_status psdproj_plan_layout(psdproj_plan_t plan, psdproj_layout* out);
  * psdproj_plan reported, 256-byte aligned, device memory.  result_dev: device memory. */
 psdproj_status psdproj_run(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp,
                            void* workspace, psdproj_result* result_dev, psdproj_stream_t stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): psdproj_run without a workspace argument.  Its workspace is a
+ * file-scope device array of PSDPROJ_STATIC_SCRATCH_BYTES (64 MiB) that each device the library
+ * runs on holds until the process ends; its header is written by a kernel that carries it in its
+ * arguments.  The call allocates nothing (no hipMalloc or hipFree, no pinned staging buffer, no
+ * event) and times nothing while kernel timing is enabled.  A, P, ld's and result_dev as for
+ * psdproj_run, and the same P bit for bit.  E_SCRATCH (synchronous, nothing enqueued) when the
+ * plan's workspace exceeds the array; psdproj_static_scratch_bytes reports both sizes (for
+ * example n = 4096, k + p = 110 needs about 31 MB in BF16X3).  Every call on a device uses that
+ * device's one array: calls on one stream run one after the other, but calls whose runs overlap
+ * on one device (other streams, other threads) race on the array and give undefined results. */
+psdproj_status psdproj_run_static(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp,
+                                  psdproj_result* result_dev, psdproj_stream_t stream);
+psdproj_status psdproj_static_scratch_bytes(psdproj_plan_t plan, size_t* needed, size_t* capacity);
 
 /* count independent projections in one grouped launch sequence (each kernel's grid covers
  * the tiles of all problems).  Arrays have count entries.  workspace_bytes must be at least

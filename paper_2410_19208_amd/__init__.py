@@ -13,7 +13,8 @@ import os
 
 __all__ = [
     "PLAIN", "SCALED", "FP64", "FP32", "BF16X3", "Desc", "Result", "Layout", "PsdprojError",
-    "lib", "psdproj_plan", "psdproj_plan_destroy", "psdproj_plan_layout", "psdproj_run",
+    "lib", "psdproj_plan", "psdproj_plan_destroy", "psdproj_plan_layout", "psdproj_run", "psdproj_run_static",
+    "psdproj_static_scratch_bytes",
     "psdproj_batch_workspace", "psdproj_batch", "psdproj_graph_create", "psdproj_graph_launch",
     "psdproj_graph_destroy", "psdproj_graph_stats", "psdproj_tile_override", "psdproj_server_create", "psdproj_submit",
     "psdproj_poll", "psdproj_wait", "psdproj_server_times", "psdproj_server_destroy",
@@ -23,7 +24,8 @@ __all__ = [
 
 PLAIN, SCALED = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
-OK, E_INVALID, E_ALPHA, E_NONFINITE, E_BREAKDOWN, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_TIMEOUT = range(10)
+(OK, E_INVALID, E_ALPHA, E_NONFINITE, E_BREAKDOWN, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_TIMEOUT,
+ E_SCRATCH) = range(11)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpsdproj.so")
 
@@ -72,6 +74,8 @@ _SIGS = {
     "psdproj_plan_destroy": (None, [_vp]),
     "psdproj_plan_layout": (_i32, [_vp, ctypes.POINTER(Layout)]),
     "psdproj_run": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
+    "psdproj_run_static": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
+    "psdproj_static_scratch_bytes": (_i32, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "psdproj_batch_workspace": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_sz)]),
     "psdproj_batch": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64),
                              ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp, _vp]),
@@ -174,6 +178,19 @@ def psdproj_plan_layout(plan) -> Layout:
 def psdproj_run(plan, A, lda, P, ldp, workspace, result_dev, stream=0) -> None:
     """All pointers are device addresses (ints); stream is a hipStream_t handle (int)."""
     _check(lib.psdproj_run(plan, A, lda, P, ldp, workspace, result_dev, stream), "psdproj_run")
+
+
+def psdproj_run_static(plan, A, lda, P, ldp, result_dev, stream=0) -> None:
+    """psdproj_run with the library's static per-device scratch array as its workspace."""
+    _check(lib.psdproj_run_static(plan, A, lda, P, ldp, result_dev, stream), "psdproj_run_static")
+
+
+def psdproj_static_scratch_bytes(plan):
+    """(bytes the plan needs, bytes the static scratch array holds)."""
+    need, cap = _sz(), _sz()
+    _check(lib.psdproj_static_scratch_bytes(plan, ctypes.byref(need), ctypes.byref(cap)),
+           "psdproj_static_scratch_bytes")
+    return need.value, cap.value
 
 
 def psdproj_batch_workspace(plans) -> int:

@@ -648,6 +648,67 @@ psdproj_status run_group(int count, const Plan* const* plans, const void* const*
   return launch_schedule(s, ws, stream);
 }
 
+// ------------------------------------------------------------------------------ static scratch
+// Header words written by a kernel that carries them in its arguments: no host staging buffer,
+// nothing allocated, an ordinary kernel on the stream.
+constexpr int FILL_WORDS = 256;
+struct FillChunk { uint32_t w[FILL_WORDS]; };
+
+__global__ __launch_bounds__(FILL_WORDS) void k_fill_words(uint32_t* __restrict__ dst, FillChunk c, int count) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = c.w[i];
+}
+
+static psdproj_status fill_by_kernel(unsigned char* dst, const void* src, size_t bytes, hipStream_t stream) {
+  const unsigned char* s = (const unsigned char*)src;
+  for (size_t o = 0; o < bytes; o += FILL_WORDS * 4) {
+    FillChunk c;
+    const size_t nb = std::min(bytes - o, (size_t)FILL_WORDS * 4);   // bytes is a multiple of 4
+    std::memcpy(c.w, s + o, nb);
+    hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(FILL_WORDS), 0, stream, (uint32_t*)(dst + o), c, (int)(nb / 4));
+    if (hipGetLastError() != hipSuccess) return PSDPROJ_E_DEVICE;
+  }
+  return PSDPROJ_OK;
+}
+
+// The workspace of psdproj_run_static: one array per device, alive until the process ends.  In
+// host code `scratch` names a host-side stand-in, not the device array: its device address comes
+// from hipGetSymbolAddress, once per device with that device current, and only that address is
+// ever handed to a kernel.
+static_assert(PSDPROJ_STATIC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[PSDPROJ_STATIC_SCRATCH_BYTES];
+
+static unsigned char* scratch_address() {
+  static std::mutex mu;
+  static std::vector<unsigned char*> addr;   // per device; null until looked up
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    addr[dev] = (unsigned char*)ptr;
+  }
+  return addr[dev];
+}
+
+psdproj_status run_static(const Plan& pl, const void* A, int64_t lda, void* P, int64_t ldp, psdproj_result* result,
+                          hipStream_t stream) {
+  if (pl.header_single + pl.region > (size_t)PSDPROJ_STATIC_SCRATCH_BYTES) return PSDPROJ_E_SCRATCH;
+  unsigned char* ws = scratch_address();
+  if (!ws) return PSDPROJ_E_DEVICE;
+  // the kernels initialise every part of the workspace they read (counters in k_setup, whole
+  // panels in k_omega), so the previous call's contents need no clearing
+  const Prob pr = make_prob(pl, ws + pl.header_single, A, lda, P, ldp, result);
+  static_assert(sizeof(Prob) % 4 == 0, "header words");
+  psdproj_status st = fill_by_kernel(ws, &pr, sizeof(Prob), stream);
+  if (st != PSDPROJ_OK) return st;
+  st = fill_by_kernel(ws + pl.single.prob_bytes, pl.single.tdata.data(), pl.single.tdata.size() * sizeof(int), stream);
+  if (st != PSDPROJ_OK) return st;
+  return enqueue(pl.single, ws, stream, /*allow_timing=*/false);
+}
+
 }  // namespace psd
 
 // ================================================================================ C ABI
@@ -697,6 +758,23 @@ psdproj_status psdproj_run(psdproj_plan_t plan, const void* A, int64_t lda, void
   if (st != PSDPROJ_OK) return st;
   return run_group(1, &pl, &A, &lda, &P, &ldp, (unsigned char*)workspace, pl->header_single + pl->region,
                    result_dev, (hipStream_t)stream);
+}
+
+psdproj_status psdproj_run_static(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp,
+                                  psdproj_result* result_dev, psdproj_stream_t stream) {
+  if (!plan || !result_dev) return PSDPROJ_E_INVALID;
+  const Plan* pl = (const Plan*)plan;
+  psdproj_status st = check_operands(*pl, A, lda, P, ldp);
+  if (st != PSDPROJ_OK) return st;
+  return run_static(*pl, A, lda, P, ldp, result_dev, (hipStream_t)stream);
+}
+
+psdproj_status psdproj_static_scratch_bytes(psdproj_plan_t plan, size_t* needed, size_t* capacity) {
+  if (!plan || !needed || !capacity) return PSDPROJ_E_INVALID;
+  const Plan* pl = (const Plan*)plan;
+  *needed = pl->header_single + pl->region;
+  *capacity = PSDPROJ_STATIC_SCRATCH_BYTES;
+  return PSDPROJ_OK;
 }
 
 psdproj_status psdproj_batch_workspace(int32_t count, const psdproj_plan_t* plans, size_t* bytes) {
@@ -819,6 +897,7 @@ const char* psdproj_status_str(psdproj_status s) {
     case PSDPROJ_E_DEVICE: return "HIP runtime error";
     case PSDPROJ_E_PENDING: return "pending";
     case PSDPROJ_E_TIMEOUT: return "timed out";
+    case PSDPROJ_E_SCRATCH: return "problem needs more workspace than the static scratch array holds";
   }
   return "unknown status";
 }

@@ -204,3 +204,4 @@ class Server:
 
     def __del__(self):
         self.close()
+
