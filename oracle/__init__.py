@@ -18,8 +18,13 @@ rnla     -- the method: range finder (Alg. 1), plain randomized projection
             exact projection (Thm 1) and the error metrics of Sec. 4.
 bounds   -- the expected-error bounds eps1/eps2 (Sec. 3.1), Cor. 1 and
             Prop. 2.
+srht     -- the structured (subsampled randomized Hadamard) test matrix, the
+            alternative to Gaussian test vectors named in Sec. 3.1.
+sdls     -- dual gradient descent for the semidefinite least-squares problem
+            (Alg. 6, supplementary SDP section), with the exact, plain or
+            scaled projection.
 
 Every function is plain FP64 numpy; LAPACK (through numpy.linalg) supplies
 the Householder QR and the symmetric eigensolver as library steps.
 """
-from . import philox, rnla, bounds  # noqa: F401
+from . import philox, srht, rnla, bounds, sdls  # noqa: F401

@@ -38,7 +38,7 @@ import dataclasses
 
 import numpy as np
 
-from . import philox
+from . import philox, srht
 
 __all__ = [
     "orth", "range_finder", "range_finder_literal", "ran_proj", "ran_proj_scal",
@@ -100,7 +100,9 @@ def range_finder_literal(X: np.ndarray, Omega: np.ndarray, q: int) -> np.ndarray
     return orth(W)
 
 
-def _omega(seed: int, n: int, r: int, omega_dtype) -> np.ndarray:
+def _omega(seed: int, n: int, r: int, omega_dtype, sketch: str = "gaussian") -> np.ndarray:
+    if sketch == "srht":
+        return srht.test_matrix(seed, n, r)          # entries +-1, exact in every precision
     om = philox.test_matrix(seed, n, r)
     return om.astype(omega_dtype).astype(np.float64)
 
@@ -123,7 +125,7 @@ def _finish(Q, C, alpha, scaled, keep_P):
 
 
 def ran_proj(X, k: int, p: int, q: int, seed: int = 0, omega_dtype=np.float64,
-             Omega: np.ndarray | None = None, keep_P: bool = True) -> ProjResult:
+             Omega: np.ndarray | None = None, keep_P: bool = True, sketch: str = "gaussian") -> ProjResult:
     """Alg. 2 (plain randomized PSD projection), oversampling l = p."""
     X = _f64(X)
     n = X.shape[0]
@@ -131,7 +133,7 @@ def ran_proj(X, k: int, p: int, q: int, seed: int = 0, omega_dtype=np.float64,
     if not (1 <= r <= n):
         raise ValueError("need 1 <= k+p <= n")
     if Omega is None:
-        Omega = _omega(seed, n, r, omega_dtype)
+        Omega = _omega(seed, n, r, omega_dtype, sketch)
     Q = range_finder(X, Omega, q)                        # Alg. 2 line 1
     C = Q.T @ (X @ Q)                                    # Q^T X Q
     return _finish(Q, C, None, False, keep_P)
@@ -139,7 +141,7 @@ def ran_proj(X, k: int, p: int, q: int, seed: int = 0, omega_dtype=np.float64,
 
 def ran_proj_scal(X, k: int, p: int, q: int, alpha: float, seed: int = 0,
                   omega_dtype=np.float64, Omega: np.ndarray | None = None,
-                  keep_P: bool = True) -> ProjResult:
+                  keep_P: bool = True, sketch: str = "gaussian") -> ProjResult:
     """Alg. 3 (scaled randomized PSD projection) for a given alpha > 0."""
     X = _f64(X)
     n = X.shape[0]
@@ -151,7 +153,7 @@ def ran_proj_scal(X, k: int, p: int, q: int, alpha: float, seed: int = 0,
     B = X / alpha                                        # Alg. 3 line 1: B = (X + alpha I)/alpha
     B[np.diag_indices(n)] = (np.diag(X) + alpha) / alpha
     if Omega is None:
-        Omega = _omega(seed, n, r, omega_dtype)
+        Omega = _omega(seed, n, r, omega_dtype, sketch)
     Q = range_finder(B, Omega, q)                        # line 2
     C = Q.T @ (B @ Q)                                    # line 3: Q^T B Q
     return _finish(Q, C, float(alpha), True, keep_P)     # line 4
@@ -185,15 +187,16 @@ def min_eig(X, N: int, seed: int = 0):
 
 def project(X, k: int, p: int, q: int, variant: str = "plain", seed: int = 0,
             alpha: float | None = None, alpha_iters: int = 10,
-            omega_dtype=np.float64, keep_P: bool = True) -> ProjResult:
+            omega_dtype=np.float64, keep_P: bool = True, sketch: str = "gaussian") -> ProjResult:
     """One call of the method as the library exposes it: plain (Alg. 2) or
-    scaled (Alg. 3 with alpha given, or estimated by Alg. 5 with N = alpha_iters)."""
+    scaled (Alg. 3 with alpha given, or estimated by Alg. 5 with N = alpha_iters);
+    sketch "gaussian" (Alg. 1's randn) or "srht" (the structured test matrix)."""
     if variant == "plain":
-        return ran_proj(X, k, p, q, seed, omega_dtype, keep_P=keep_P)
+        return ran_proj(X, k, p, q, seed, omega_dtype, keep_P=keep_P, sketch=sketch)
     s1 = s2 = None
     if alpha is None or alpha <= 0.0:
         alpha, s1, s2 = min_eig(X, alpha_iters, seed)
-    res = ran_proj_scal(X, k, p, q, alpha, seed, omega_dtype, keep_P=keep_P)
+    res = ran_proj_scal(X, k, p, q, alpha, seed, omega_dtype, keep_P=keep_P, sketch=sketch)
     res.sigma1, res.sigma2 = s1, s2
     return res
 

@@ -25,6 +25,8 @@ import pytest
 import test_oracle_bounds as TB
 import test_oracle_method as TM
 import test_oracle_philox as TP
+import test_oracle_sdls as TS
+import test_oracle_srht as TR
 
 ORACLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
 
@@ -71,6 +73,17 @@ PINS = {
     "philox_kat0": lambda: TP.test_philox_known_answers(*TP.KAT[0]),
     "philox_kat2": lambda: TP.test_philox_known_answers(*TP.KAT[2]),
     "gauss_stats": lambda: TP.test_gaussian_statistics(),
+    "srht_bijection_odd": lambda: TR.test_column_permutation_is_a_bijection(5),
+    "srht_bijection_even": lambda: TR.test_column_permutation_is_a_bijection(6),
+    "srht_sylvester": lambda: TR.test_hadamard_against_sylvester_construction(),
+    "srht_orthogonal": lambda: TR.test_power_of_two_order_gives_orthogonal_columns(64, 20),
+    "srht_signs": lambda: TR.test_signs_are_balanced(),
+    "srht_recovery": lambda: TR.test_exact_recovery_with_structured_sketch(),
+    "sdls_gradient": lambda: TS.test_gradient_is_minus_constraint_residual(),
+    "sdls_feasible": lambda: TS.test_exact_gd_reaches_feasibility(),
+    "sdls_scalar_root": lambda: TS.test_single_constraint_against_scalar_root(),
+    "sdls_hook": lambda: TS.test_randomized_gd_follows_the_projection_it_is_given(),
+    "sdls_loop": lambda: TS.test_loop_runs_at_most_m_iterations_and_at_least_one(),
 }
 
 # (id, oracle file, text, replacement, pins expected to notice)
@@ -118,6 +131,22 @@ MUTANTS = [
     ("philox_round_swap", "philox.py", "hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0", "hi0 ^ c1 ^ k0, lo1, hi1 ^ c3 ^ k1, lo0",
      ["philox_kat0", "philox_kat2"]),
     ("box_muller_radius", "philox.py", "np.sqrt(-2.0 * np.log(u1))", "np.sqrt(-np.log(u1))", ["gauss_stats"]),
+    ("srht_no_cycle_walk", "srht.py", "    while y >= (1 << m):\n        y = feistel(seed, y, m)\n", "",
+     ["srht_bijection_odd"]),
+    ("srht_parity", "srht.py", "par ^= v & 1", "par += v & 1", ["srht_sylvester", "srht_orthogonal"]),
+    ("srht_feistel_round", "srht.py", "L, R = R, L ^ f", "L, R = R, R ^ f", ["srht_bijection_odd", "srht_bijection_even"]),
+    ("srht_sign_bit", "srht.py", "(w[:, 0] & 1)", "(w[:, 0] & 0)", ["srht_signs"]),
+    ("srht_not_used", "rnla.py", "        return srht.test_matrix(seed, n, r)", "        return philox.test_matrix(seed, n, r)",
+     ["srht_recovery"]),
+    ("sdls_update_sign", "sdls.py", "y = y - beta * g  ", "y = y + beta * g  ",
+     ["sdls_feasible", "sdls_scalar_root", "sdls_hook"]),
+    ("sdls_rho_dropped", "sdls.py", "X = np.asarray(C, np.float64) / rho", "X = np.asarray(C, np.float64)",
+     ["sdls_gradient", "sdls_scalar_root"]),
+    ("sdls_residual_sign", "sdls.py", "for Ai in A]) - np.asarray(b, np.float64)",
+     "for Ai in A]) + np.asarray(b, np.float64)", ["sdls_gradient", "sdls_feasible", "sdls_scalar_root"]),
+    ("sdls_seed_offset", "sdls.py", "X_plus = rnla.ran_proj(X, k, p, q, seed=seed + i - 1,",
+     "X_plus = rnla.ran_proj(X, k, p, q, seed=seed + i,", ["sdls_hook"]),
+    ("sdls_extra_iteration", "sdls.py", "while i < M and", "while i <= M and", ["sdls_loop"]),
 ]
 
 
@@ -130,6 +159,10 @@ def test_planted_mistake_fails_a_pin(mid, fname, old, new, pins, monkeypatch):
             monkeypatch.setattr(test_mod, "bounds", mod.bounds)
         for test_mod in (TM, TP):
             monkeypatch.setattr(test_mod, "philox", mod.philox)
+        monkeypatch.setattr(TS, "rnla", mod.rnla)
+        monkeypatch.setattr(TS, "sdls", mod.sdls)
+        monkeypatch.setattr(TR, "rnla", mod.rnla)
+        monkeypatch.setattr(TR, "srht", mod.srht)
         caught = []
         for name in pins:
             try:
@@ -151,6 +184,10 @@ def test_unmutated_copy_passes_every_pin(monkeypatch):
             monkeypatch.setattr(test_mod, "bounds", mod.bounds)
         for test_mod in (TM, TP):
             monkeypatch.setattr(test_mod, "philox", mod.philox)
+        monkeypatch.setattr(TS, "rnla", mod.rnla)
+        monkeypatch.setattr(TS, "sdls", mod.sdls)
+        monkeypatch.setattr(TR, "rnla", mod.rnla)
+        monkeypatch.setattr(TR, "srht", mod.srht)
         for name, pin in PINS.items():
             pin()
     finally:

@@ -29,7 +29,8 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "haar_orthogonal", "from_spectrum",
     "spectrum_small", "spectrum_medium", "spectrum_large", "spectrum_batched",
-    "cor2_spectrum", "make_matrix", "batched_problem_sizes", "serving_requests",
+    "cor2_spectrum", "make_matrix", "batched_problem_sizes", "serving_requests", "sdls_problem",
+    "sparse_symmetric",
 ]
 
 
@@ -217,3 +218,49 @@ def serving_requests(count: int, qps: float, seed: int, nmin: int = 256, nmax: i
         variant = "scaled" if g.random() < 0.5 else "plain"
         out.append((t, n, k, p, q, variant))
     return out
+
+
+def sdls_problem(n: int, m: int, seed: int, dtype=np.float64):
+    """Synthetic SDLS instance after the recipe of the supplementary SDP section's first example:
+    A_i = (G_i + G_i^T) / (2 ||G_i||_F) with G_i N(0,1) n x n; a PSD X0 = H H^T / n (H N(0,1))
+    and b_i = Tr(A_i X0), so the problem is feasible; C = (K + K^T) / (2 sqrt(n)) with K N(0,1);
+    y0 ~ N(0,1) (the random initialisation of the dual iterate).  Returns (C, A (m x n x n), b,
+    y0), C and A in `dtype`, b and y0 computed in float64 from the stored A."""
+    g = _rng(seed)
+    A = np.empty((m, n, n), dtype=dtype)
+    for i in range(m):
+        G = g.standard_normal((n, n))
+        A[i] = ((G + G.T) / (2.0 * np.linalg.norm(G))).astype(dtype)
+    H = g.standard_normal((n, n))
+    X0 = H @ H.T / n
+    K = g.standard_normal((n, n))
+    C = ((K + K.T) / (2.0 * math.sqrt(n))).astype(dtype)
+    b = np.array([float(np.sum(A[i].astype(np.float64) * X0)) for i in range(m)])
+    y0 = g.standard_normal(m)
+    return C, A, b, y0
+
+
+def sparse_symmetric(n: int, per_row: int, seed: int, dtype=np.float64):
+    """Sparse symmetric stand-in for the paper's sparse benchmark matrices (Sec. 4, Table 1,
+    which are not available here): off-diagonal pattern of about per_row random entries per row
+    (N(0,1) / sqrt(per_row), symmetrised), diagonal with 5% of its entries decaying from 10 to
+    1e-4 and the rest uniform in [-1, 0], the spectral character of the large dense stand-in.
+    Returns (row_ptr int32 (n+1), col_idx int32, vals (dtype)) in CSR form with both triangles
+    stored, columns sorted within each row, and the same matrix dense in float64 (from the
+    stored values)."""
+    import scipy.sparse as sp
+    g = _rng(seed)
+    half = max(1, per_row // 2)
+    rows = np.repeat(np.arange(n), half)
+    cols = g.integers(0, n, size=n * half)
+    vals = g.standard_normal(n * half) / math.sqrt(per_row)
+    S = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    n_pos = max(1, int(round(0.05 * n)))
+    d = np.concatenate([10.0 * 10.0 ** (-5.0 * np.arange(n_pos) / max(n_pos - 1, 1)), -g.random(n - n_pos)])
+    d = d[g.permutation(n)]
+    A = ((S + S.T) * 0.5 + sp.diags(d)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    vals = A.data.astype(dtype)
+    dense = sp.csr_matrix((vals.astype(np.float64), A.indices, A.indptr), shape=(n, n)).toarray()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), vals, dense
