@@ -93,11 +93,15 @@ def parse():
                          "overlaps the next step's streaming kernels (1: one stream)")
     ap.add_argument("--sequential", action="store_true",
                     help="time the step as two psdproj_run calls instead of one grouped psdproj_batch")
-    ap.add_argument("--mode", default="step", choices=["step", "batch", "serve", "counters"],
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "batch", "serve", "counters", "exact", "sdls", "sparse", "sketch"],
                     help="step: the headline n=20000 step (default); batch: 256 uneven problems in one "
                          "grouped launch sequence; serve: Poisson arrivals through the request server; "
                          "counters: a short run for hardware-counter profiles (symmetric Gaussian A, no QR "
-                         "in the generator, two grouped steps, then one 1 GiB device copy for calibration)")
+                         "in the generator, two grouped steps, then one 1 GiB device copy for calibration); "
+                         "exact: the exact projection (Thm 1) against the randomized ones at n=4096; sdls: "
+                         "dual gradient descent (Alg. 6) iterations; sparse: the headline step on a sparse A; "
+                         "sketch: the headline step with the structured test matrix")
     ap.add_argument("--qps", default="50,100,200,500,1000,2000", help="serve mode: arrival rates")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests per arrival rate (at most) in serve mode and in the serving leg of the step")
@@ -129,6 +133,14 @@ def main() -> int:
         return run_serve(args, dev)
     if args.mode == "counters":
         return run_counters(args, dev)
+    if args.mode == "exact":
+        return run_exact(args, dev)
+    if args.mode == "sdls":
+        return run_sdls(args, dev)
+    if args.mode == "sparse":
+        return run_sparse(args, dev)
+    if args.mode == "sketch":
+        return run_sketch(args, dev)
     n, k, p, q = args.n, args.k, args.p, args.q
     r = k + p
 
@@ -664,6 +676,345 @@ def run_serve(args, dev) -> int:
            "points": points, "fp32_one_at_a_time": base}
     print(json.dumps(out), flush=True)
     return 0 if all(pt["errors"] == 0 for pt in points + base) else 1
+
+
+# ------------------------------------------------------------------------------ helpers of the modes below
+def kernel_table(pp, fn, reps):
+    """Device time per kernel kind over `reps` calls of fn (every launch timed by the library)."""
+    import torch
+    pp.psdproj_profile_select(None)
+    pp.psdproj_profile_reset()
+    pp.psdproj_profile_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    pp.psdproj_profile_enable(False)
+    out = {}
+    for kind in range(pp.psdproj_kernel_kinds()):
+        ms, cnt = pp.psdproj_profile_read(kind)
+        if cnt:
+            out[pp.psdproj_kernel_name(kind)] = {"avg_us": round(1e3 * ms / cnt, 2),
+                                                  "launches_per_call": cnt / reps, "ms_per_call": round(ms / reps, 4)}
+    return out
+
+
+def timed(fn, reps, warm=1):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def host_cores():
+    try:
+        import threadpoolctl
+        return max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:
+        return os.cpu_count()
+
+
+def roofline_entry(kernel, avg_us, work, bound, peak, unit, model):
+    ach = work / (avg_us * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
+    return {"bound": bound, "kernel": kernel, "achieved": round(ach, 1), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": None, "avg_launch_us": avg_us,
+            ("algorithmic_flops_per_launch" if unit == "TFLOP/s" else "algorithmic_bytes_per_launch"): work,
+            "model": model}
+
+
+FP64_CU_TFLOPS = FP64_PEAK_TFLOPS / 256.0   # one compute unit's share of the FP64 vector peak
+
+
+def tridiag_roofline(kern, r, problems_per_launch):
+    """k_tridiag runs one workgroup (one CU) per problem: its work is the (4/3) r^3 flops of the
+    Householder reduction, against the FP64 rate of the CUs it occupies."""
+    d = kern["k_tridiag"]
+    flops = 4.0 / 3.0 * r ** 3 * problems_per_launch
+    e = roofline_entry("k_tridiag", d["avg_us"], flops, "alu", round(FP64_CU_TFLOPS * problems_per_launch, 4),
+                       "TFLOP/s", "(4/3) r^3 flops per problem, one workgroup (one CU) per problem")
+    return e
+
+
+def run_exact(args, dev) -> int:
+    """The exact projection (Thm 1; the scal = -1 branch of Alg. 6), computed on the GPU through
+    the sign function (scaled Newton-Schulz, FP64 GEMMs on the matrix cores), against the
+    randomized projections on the same n = 4096 matrix (the medium workload: 200 eigenvalues 1/i,
+    the rest uniform in [-0.5, 0], Gaussian noise 1e-3/sqrt(n)): the O(n^3) versus O(k n^2) cost
+    the paper states and does not time."""
+    import numpy as np
+    import torch
+
+    import paper_2410_19208_amd as pp
+    import workloads
+    from oracle import rnla
+    from paper_2410_19208_amd.torch_api import ExactProjector, Projector
+
+    n = 4096
+    U = workloads.haar_orthogonal(n, 0, device="cuda")
+    lam = workloads.spectrum_medium(n, 200, 0)
+    A64 = workloads.from_spectrum(U, lam)
+    del U
+    ex = ExactProjector(n, "fp64", device=dev)
+    P = ex(A64)
+    torch.cuda.synchronize()
+    if ex.result().status:
+        log(f"exact projection status {ex.result().status}")
+        return 1
+    reps = max(2, args.steps // 5)
+    t_exact = timed(lambda: ex(A64, P), reps)
+    kern = kernel_table(pp, lambda: ex(A64, P), 1)
+    gemm = kern["k_gemm64"]
+    rf = roofline_entry("k_gemm64", gemm["avg_us"], 2.0 * n ** 3, "mfma", FP64_PEAK_TFLOPS, "TFLOP/s",
+                        "one n x n x n FP64 product (2 n^3 flops) per launch")
+    A32 = A64.to(torch.float32)
+    rnd = {}
+    for prec, A in (("fp64", A64), ("fp32", A32), ("bf16x3", A32)):
+        pr = Projector(n, 100, 10, 1, "scaled", prec, seed=0, alpha=0.0, device=dev)
+        rnd[prec] = round(1e3 * timed(lambda: pr(A), reps), 3)
+    # accuracy of the GPU exact projection against the oracle's eigendecomposition (host, FP64)
+    A_host = A64.cpu().numpy()
+    t0 = time.perf_counter()
+    ref = rnla.exact_projection(A_host)
+    cpu_s = time.perf_counter() - t0
+    err = float(np.linalg.norm(P.cpu().numpy() - ref) / np.linalg.norm(ref))
+    out = {"metric": "exact PSD projections/s (Thm 1 on the GPU) at n=4096, with the randomized ones beside it",
+           "value": round(1.0 / t_exact, 3), "unit": "projections/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "medium_4096: n=4096, 200 eigenvalues 1/i, rest U[-0.5,0], noise 1e-3/sqrt(n); "
+                                  "exact = sign-function iteration, FP64"},
+           "ms_exact": round(1e3 * t_exact, 3), "gemms_per_projection": gemm["launches_per_call"],
+           "ms_randomized_scaled_k100_p10_q1": rnd, "speedup_randomized_bf16x3": round(1e3 * t_exact / rnd["bf16x3"], 1),
+           "parity_vs_eigendecomposition": err, "tol": PARITY_TOL["fp64"], "r_plus": ex.result().r_plus,
+           "roofline": rf, "kernels": kern,
+           "cpu_baseline": {"value": round(1.0 / cpu_s, 4), "unit": "projections/s", "cores": int(host_cores()),
+                            "kind": "oracle", "sample": f"one exact projection (numpy eigh) of the same n={n} matrix, "
+                                                        f"{cpu_s:.1f} s"}}
+    print(json.dumps(out), flush=True)
+    return 0 if err < PARITY_TOL["fp64"] else 1
+
+
+def run_sdls(args, dev) -> int:
+    """Dual gradient descent for an SDLS problem (Alg. 6) with the scaled randomized projection
+    (scal = 1: Alg. 5 + Alg. 3 every iteration), n = 4096, m = 8 constraints, k = 100, l = 10,
+    q = 1, BF16x3, after the synthetic recipe of the supplementary SDP section's first example
+    (normalised symmetric Gaussian A_i, b from a random PSD X0, random symmetric C), a fixed number
+    of iterations (eps = 0); the exact-projection descent (scal = -1) timed beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2410_19208_amd as pp
+    import workloads
+    from oracle import sdls
+    from paper_2410_19208_amd.torch_api import SdlsSolver
+
+    n, m, k, p, q, iters = 4096, 8, 100, 10, 1, 10
+    C, A, b, y0 = workloads.sdls_problem(n, m, 77, dtype=np.float32)
+    Cd, Ad = torch.from_numpy(C).to(dev), torch.from_numpy(A).to(dev)
+    bt, yt = torch.from_numpy(b), torch.from_numpy(y0)
+    solver = SdlsSolver(n, m, k, p, q, 1, "bf16x3", 10, iters, 1.0, 0.5, 0.0, 3, device=dev)
+    y, X, info = solver.solve(Cd, Ad, bt, yt)
+    t0 = time.perf_counter()
+    y, X, info = solver.solve(Cd, Ad, bt, yt)
+    t_solve = time.perf_counter() - t0
+    if info.status:
+        log(f"sdls status {info.status}")
+        return 1
+    kern = kernel_table(pp, lambda: solver.solve(Cd, Ad, bt, yt), 1)
+    dom = max(kern, key=lambda kk: kern[kk]["ms_per_call"])
+    per_iter = {kk: v["launches_per_call"] / iters for kk, v in kern.items()}
+    es = 4
+    models = {"k_pass": (n * n * es * 2 * (q + 1) / per_iter.get("k_pass", 1), "one read of A per pass"),
+              "k_gemv": (n * (n + 1) / 2 * es + 2 * n * 8, "upper triangle of X per product"),
+              "k_rebuild": (n * n * es, "P written once"),
+              "k_sdls_form": ((m + 2) * n * n * es, "C and the A_i read, X written"),
+              "k_sdls_trace": ((m + 1) * n * n * es, "the A_i and P read")}
+    if dom == "k_tridiag":
+        rf = tridiag_roofline(kern, k + p, 1)
+    else:
+        work, model = models.get(dom, (float("nan"), "no byte model"))
+        rf = roofline_entry(dom, kern[dom]["avg_us"], work, "hbm", HBM_PEAK_GBS, "GB/s", model)
+    ex_solver = SdlsSolver(n, m, 0, 0, 0, -1, "bf16x3", 10, 2, 1.0, 0.5, 0.0, 3, device=dev)
+    ex_solver.solve(Cd, Ad, bt, yt)
+    t0 = time.perf_counter()
+    _, _, info_ex = ex_solver.solve(Cd, Ad, bt, yt)
+    t_ex = (time.perf_counter() - t0) / 2
+    # oracle: one iteration on the host, and the GPU's first iterate against it
+    one = SdlsSolver(n, m, k, p, q, 1, "bf16x3", 10, 1, 1.0, 0.5, 0.0, 3, device=dev)
+    y1, _, _ = one.solve(Cd, Ad, bt, yt)
+    t0 = time.perf_counter()
+    ref = sdls.dual_gd(C, A, b, 1.0, k, p, q, 10, 1, 0.0, 0.5, 1, y0, seed=3, omega_dtype=np.float32,
+                       storage_dtype=np.float32)
+    cpu_s = time.perf_counter() - t0
+    dy = float(np.max(np.abs(y1.cpu().numpy() - ref.y)))
+    out = {"metric": "SDLS dual gradient descent iterations/s (Alg. 6, scaled randomized projection)",
+           "value": round(iters / t_solve, 3), "unit": "iterations/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "bf16x3", "data": "synthetic",
+           "config": {"workload": f"sdls: n={n}, m={m}, k={k}, l={p}, q={q}, scal=1 (alpha by Alg. 5, N=10), rho=1, "
+                                  f"beta=0.5, {iters} iterations; A_i normalised symmetric Gaussian, b from a random "
+                                  f"PSD X0"},
+           "ms_per_iteration": round(1e3 * t_solve / iters, 3),
+           "ms_per_iteration_exact_projection": round(1e3 * t_ex, 3), "grad_norm": info.grad_norm,
+           "first_iterate_max_abs_diff_vs_oracle": dy, "roofline": rf, "kernels": kern,
+           "cpu_baseline": {"value": round(1.0 / cpu_s, 4), "unit": "iterations/s", "cores": int(host_cores()),
+                            "kind": "oracle", "sample": f"one iteration of the oracle's dual_gd on the same problem, "
+                                                        f"{cpu_s:.1f} s"}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _step_pair_mode(args, dev, name, make_pair, bytes_model, note):
+    """Shared body of the sparse and structured-sketch modes: steps of one plain + one scaled
+    projection, the kernel table, the dominant kernel's roofline, parity with the oracle."""
+    import numpy as np
+    import torch
+
+    import paper_2410_19208_amd as pp
+    from oracle import rnla
+    run, results, outputs, oracle_pair, dense_A = make_pair()
+    run()
+    torch.cuda.synchronize()
+    st = [r.status for r in results()]
+    if any(st):
+        log(f"{name}: device status {st}")
+        return 1
+    t_step = timed(run, args.steps)
+    kern = kernel_table(pp, run, max(2, args.steps // 4))
+    dom = max(kern, key=lambda kk: kern[kk]["ms_per_call"])
+    if dom == "k_tridiag":
+        rf = tridiag_roofline(kern, args.k + args.p, 1)
+    else:
+        work, model = bytes_model(dom, kern)
+        rf = roofline_entry(dom, kern[dom]["avg_us"], work, "hbm", HBM_PEAK_GBS, "GB/s", model)
+    # the streaming kernels against the HBM roofline as well
+    stream = {}
+    for kk in ("k_pass", "k_gemv", "k_rebuild"):
+        if kk in kern:
+            w, m = bytes_model(kk, kern)
+            stream[kk] = roofline_entry(kk, kern[kk]["avg_us"], w, "hbm", HBM_PEAK_GBS, "GB/s", m)
+    out = {"metric": f"PSD projections/s ({note})", "value": round(2.0 / t_step, 3), "unit": "projections/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": name}, "ms_per_step": round(1e3 * t_step, 3),
+           "r_plus": [r.r_plus for r in results()], "roofline": rf, "a_streaming": stream, "kernels": kern}
+    if not args.no_cpu_baseline:
+        A_host = dense_A()
+        t0 = time.perf_counter()
+        refs = oracle_pair(A_host)
+        cpu_s = time.perf_counter() - t0
+        a_fro = float(np.linalg.norm(A_host))
+        par = [rnla.parity_error(o.cpu().numpy().astype(np.float64), r.P, a_fro) for o, r in zip(outputs(), refs)]
+        out["parity"] = {"plain": par[0], "scaled": par[1], "tol": PARITY_TOL[args.precision]}
+        out["cpu_baseline"] = {"value": round(2.0 / cpu_s, 5), "unit": "projections/s", "cores": int(host_cores()),
+                               "kind": "oracle", "sample": f"one plain + one scaled projection, {cpu_s:.1f} s"}
+        if max(par) >= PARITY_TOL[args.precision]:
+            print(json.dumps(out), flush=True)
+            return 1
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_sparse(args, dev) -> int:
+    """The headline parameters (n = 20000, k = 200, p = 20, q = 1, plain + scaled with alpha by
+    Alg. 5) on a sparse symmetric A (CSR, about 32 stored entries per row, the spectral character
+    of the dense stand-in on the diagonal): the paper's benchmark matrices are sparse."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from oracle import rnla
+    from paper_2410_19208_amd.torch_api import SparseProjector
+
+    n, k, p, q, per_row = args.n, args.k, args.p, args.q, 32
+    prec = args.precision
+    dt = np.float64 if prec == "fp64" else np.float32
+    rp, ci, v, D = workloads.sparse_symmetric(n, per_row, 8001, dt)
+    nnz = len(ci)
+    del D
+    rpd, cid, vd = (torch.from_numpy(x).to(dev) for x in (rp, ci, v))
+    s1 = SparseProjector(n, k, p, q, "plain", prec, seed=args.seed, device=dev)
+    s2 = SparseProjector(n, k, p, q, "scaled", prec, seed=args.seed, alpha=0.0, alpha_iters=args.alpha_iters, device=dev)
+    P1 = torch.empty((n, n), dtype=vd.dtype, device=dev)
+    P2 = torch.empty_like(P1)
+
+    def make_pair():
+        def run():
+            s1(rpd, cid, vd, P1)
+            s2(rpd, cid, vd, P2)
+
+        def dense():
+            return workloads.sparse_symmetric(n, per_row, 8001, dt)[3]
+
+        def oracle_pair(Ah):
+            return (rnla.project(Ah, k, p, q, "plain", seed=args.seed, omega_dtype=dt),
+                    rnla.project(Ah, k, p, q, "scaled", seed=args.seed, alpha_iters=args.alpha_iters, omega_dtype=dt))
+        return run, lambda: (s1.result(), s2.result()), lambda: (P1, P2), oracle_pair, dense
+
+    es = 8 if prec == "fp64" else 4
+
+    def bytes_model(dom, kern):
+        per_problem = {"k_rebuild": (float(n) * n * es, "P written once"),
+                       "k_pass": (nnz * (4 + es) + (n + 1) * 4 + n * (k + p) * es,
+                                  "the CSR arrays and the panel read once per pass"),
+                       "k_gemv": (nnz * (4 + es) + (n + 1) * 4 + 2 * n * 8, "the CSR arrays and two vectors")}
+        w, m = per_problem.get(dom, (float("nan"), "no byte model"))
+        lpc = kern[dom]["launches_per_call"]
+        problems = {"k_rebuild": 2, "k_pass": 2 * (2 * q + 2), "k_gemv": 2 * (args.alpha_iters + 1)}.get(dom, lpc)
+        return w * problems / lpc, m
+    return _step_pair_mode(args, dev, f"sparse_20k: n={n}, {nnz / n:.1f} stored entries per row (CSR, both "
+                                      f"triangles), k={k}, p={p}, q={q}; one plain + one scaled projection per step",
+                           make_pair, bytes_model, "sparse A, CSR")
+
+
+def run_sketch(args, dev) -> int:
+    """The headline step with the structured (subsampled randomized Hadamard) test matrix in place
+    of the Gaussian one (Sec. 3.1's footnote): same matrix, same parameters."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from oracle import rnla
+    from paper_2410_19208_amd.torch_api import Projector
+
+    n, k, p, q = args.n, args.k, args.p, args.q
+    U = workloads.haar_orthogonal(n, 3001, device="cuda")
+    lam = workloads.spectrum_large(n, 0.05, 3001)
+    A = workloads.from_spectrum(U, lam).to(torch.float32 if args.precision != "fp64" else torch.float64)
+    del U
+    dt = np.float64 if args.precision == "fp64" else np.float32
+    s1 = Projector(n, k, p, q, "plain", args.precision, seed=args.seed, device=dev, sketch="srht")
+    s2 = Projector(n, k, p, q, "scaled", args.precision, seed=args.seed, alpha=0.0, alpha_iters=args.alpha_iters,
+                   device=dev, sketch="srht")
+    P1, P2 = torch.empty_like(A), torch.empty_like(A)
+
+    def make_pair():
+        def run():
+            s1(A, P1)
+            s2(A, P2)
+
+        def oracle_pair(Ah):
+            return (rnla.project(Ah, k, p, q, "plain", seed=args.seed, omega_dtype=dt, sketch="srht"),
+                    rnla.project(Ah, k, p, q, "scaled", seed=args.seed, alpha_iters=args.alpha_iters, omega_dtype=dt,
+                                 sketch="srht"))
+        return run, lambda: (s1.result(), s2.result()), lambda: (P1, P2), oracle_pair, \
+            lambda: A.cpu().numpy().astype(np.float64)
+
+    es = 8 if args.precision == "fp64" else 4
+
+    def bytes_model(dom, kern):
+        lpc = kern[dom]["launches_per_call"]
+        per = {"k_pass": (float(n) * n * es, 2 * (2 * q + 2), "one read of A per pass and problem"),
+               "k_gemv": (n * (n + 1) / 2 * es + 2 * n * 8, 2 * (args.alpha_iters + 1), "upper triangle per product"),
+               "k_rebuild": (float(n) * n * es, 2, "P written once")}
+        if dom not in per:
+            return float("nan"), "no byte model"
+        w, problems, m = per[dom]
+        return w * problems / lpc, m
+    return _step_pair_mode(args, dev, f"large_20k with the structured test matrix: n={n}, k={k}, p={p}, q={q}; "
+                                      f"one plain + one scaled projection per step (two runs)",
+                           make_pair, bytes_model, "structured subsampled-Hadamard test matrix")
 
 
 if __name__ == "__main__":

@@ -105,8 +105,25 @@ typedef struct {
     uint64_t seed;        /* Philox key for the test matrix and power-iteration starts */
     double   alpha;       /* scaled: > 0 use as given; <= 0 estimate with Alg. 5 */
     int32_t  alpha_iters; /* N of Alg. 4/5 when alpha is estimated, 1..1000 (paper: 10) */
-    uint32_t flags;       /* reserved, must be 0 */
+    uint32_t flags;       /* PSDPROJ_FLAG_* (other bits must be 0) */
 } psdproj_desc;
+
+/* flags: the test matrix of Alg. 1 is the structured one of Sec. 3.1's footnote (a subsampled
+ * randomized Hadamard transform, the real form of the SRFT) instead of Gaussian:
+ *   Omega[i][j] = d_i (-1)^popcount(i & s_j), entries exactly +1 or -1 (the transform's
+ *   normalisation is left out: only range(X Omega) is used), d_i = +-1 from the low bit of
+ *   Philox word x0 of counter i in stream 3, and s_j = pi(j) for a permutation pi of [0, 2^m),
+ *   2^m >= n (m >= 1): a four-round Feistel network on m + (m mod 2) bits (round t adds the low
+ *   half-width bits of word x0 of counter t 2^(half width) + R, stream 4, to the left half),
+ *   re-applied while the value is 2^m or more.  The matrix is formed on the device and applied
+ *   by the same passes as a Gaussian one. */
+#define PSDPROJ_FLAG_SRHT 1u
+/* flags: the plan is for a sparse A given to psdproj_run_csr (and only there): A in CSR form with
+ * both triangles of the symmetric matrix stored.  The passes of Alg. 1-3 then add a_ij Z[j, :]
+ * over the stored nonzeros (FP64 for FP64 storage, FP32 for FP32 and BF16X3, whose split
+ * products are not used) and the power iterations of Alg. 4 use the sparse product; every other
+ * step, and P (dense n x n), are as for a dense A. */
+#define PSDPROJ_FLAG_CSR 2u
 
 /* Written by the device at the end of a run (read it after synchronising). */
 typedef struct {
@@ -150,6 +167,16 @@ psdproj_status psdproj_plan_layout(psdproj_plan_t plan, psdproj_layout* out);
  * psdproj_plan reported, 256-byte aligned, device memory.  result_dev: device memory. */
 psdproj_status psdproj_run(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp,
                            void* workspace, psdproj_result* result_dev, psdproj_stream_t stream);
+
+/* One projection of a sparse symmetric A (plan created with PSDPROJ_FLAG_CSR): row_ptr (n + 1
+ * int32, non-decreasing), col_idx (nnz int32 in [0, n)) and vals (nnz double for FP64, float
+ * otherwise) in device memory, both triangles stored.  P is the dense n x n result (row stride
+ * ldp, 16-byte aligned, not overlapping vals), workspace as for psdproj_run.  Column indices
+ * outside [0, n) and row ranges outside [0, nnz) are skipped and reported as E_INVALID in
+ * result_dev->status. */
+psdproj_status psdproj_run_csr(psdproj_plan_t plan, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                               int64_t nnz, void* P, int64_t ldp, void* workspace, psdproj_result* result_dev,
+                               psdproj_stream_t stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation): psdproj_run without a workspace argument.  Its workspace is a
@@ -198,6 +225,55 @@ psdproj_status psdproj_graph_launch(psdproj_graph_t graph, psdproj_stream_t stre
 void           psdproj_graph_destroy(psdproj_graph_t graph);
 psdproj_status psdproj_graph_stats(int64_t* captures, int64_t* replays);
 
+/* The exact projection X_+ = U max(D, 0) U^T of Thm 1 (the scal = -1 branch of Alg. 6, and the
+ * O(n^3) reference the randomized projections are measured against).  Computed without an
+ * eigendecomposition, through the polar form X_+ = (X + |X|) / 2 with |X| = X sign(X) and sign(X)
+ * by the scaled Newton-Schulz iteration started from X / ||X||_F, every product an n x n FP64
+ * GEMM on the matrix cores.  Eigenvalues with |lambda| >= l0 ||X||_F converge to round-off (l0 =
+ * 1e-13 for FP64 storage, 1e-9 for FP32 / BF16X3); each smaller one adds at most l0 ||X||_F / 2
+ * to the error.  A, P: n x n symmetric, double (FP64) or float (FP32, BF16X3), row strides lda,
+ * ldp; P may alias A exactly.  workspace: psdproj_exact_workspace bytes (4 n^2 doubles and a
+ * little more), 256-byte aligned.  result_dev->r_plus receives the number of positive eigenvalues
+ * (round(Tr(I + sign X) / 2)); status NONFINITE when ||X||_F is not finite.  n <= 65535. */
+psdproj_status psdproj_exact_workspace(int64_t n, int32_t precision, size_t* bytes);
+psdproj_status psdproj_exact(int64_t n, int32_t precision, const void* A, int64_t lda, void* P, int64_t ldp,
+                             void* workspace, size_t workspace_bytes, psdproj_result* result_dev,
+                             psdproj_stream_t stream);
+
+/* Dual gradient descent for the semidefinite least-squares problem (Alg. 6, supplementary SDP
+ * section):  min over PSD X of 1/2 ||X - C/rho||_F^2  subject to  Tr(A_i^T X) = b_i, i = 1..m.
+ * Iteration it (1-based) forms X = C/rho + sum_i y_i A_i, projects it (scal = 0: Alg. 2;
+ * scal = 1: Alg. 3 with alpha by Alg. 5, N = alpha_iters; scal = -1: the exact projection of
+ * Thm 1), forms g_i = Tr(A_i^T Xhat_+) - b_i and updates y <- y - beta g.  The projection of
+ * iteration it draws its random numbers from Philox key seed + it - 1.  The loop stops after the
+ * first iteration whose ||g||_2 <= eps, or after max_iters iterations (at least one runs).
+ * Storage: C, the A_i and X in double (precision FP64) or float (FP32, BF16X3); A_i at
+ * A + i * a_stride elements with row stride lda; b (m doubles) and y (m doubles: the initial
+ * iterate in, the final one out) in device memory; X (n x n, row stride ldx) receives the last
+ * projection, the approximate primal solution.  The call runs the iterations on `stream` and
+ * synchronises with it once per iteration to read ||g||; info (host memory) receives the status
+ * (a device error of a projection stops the loop), the iterations run and the last ||g||. */
+typedef struct {
+    int64_t  n;           /* order, 1 .. 65535 */
+    int32_t  m;           /* number of constraints, >= 1 */
+    int32_t  k, p, q;     /* projection parameters as in psdproj_desc (unused for scal = -1) */
+    int32_t  scal;        /* -1 exact (Thm 1), 0 Alg. 2, 1 Alg. 3 */
+    int32_t  precision;   /* psdproj_precision */
+    int32_t  alpha_iters; /* N of Alg. 5 (scal = 1) */
+    int32_t  max_iters;   /* M, >= 1 */
+    uint32_t flags;       /* reserved, must be 0 */
+    double   rho;         /* > 0 */
+    double   beta;        /* step size, > 0 */
+    double   eps;         /* stopping tolerance on ||g||_2, >= 0 */
+    uint64_t seed;
+} psdproj_sdls_desc;
+typedef struct { int32_t status; int32_t iters; double grad_norm; } psdproj_sdls_info;
+psdproj_status psdproj_sdls_workspace(const psdproj_sdls_desc* desc, size_t* bytes);
+psdproj_status psdproj_sdls_solve(const psdproj_sdls_desc* desc, const void* C, int64_t ldc, const void* A,
+                                  int64_t lda, int64_t a_stride, const double* b_dev, double* y_dev, void* X,
+                                  int64_t ldx, void* workspace, size_t workspace_bytes, psdproj_sdls_info* info,
+                                  psdproj_stream_t stream);
+
 /* Continuous-batching request server on the current device (the batching of many independent
  * projections, each one Alg. 1 + Alg. 2 or Alg. 3).  hbm_budget_bytes of device memory is
  * allocated at creation and holds the workspaces of the requests in flight.  Requests are
@@ -227,6 +303,9 @@ void           psdproj_server_destroy(psdproj_server_t server);
 /* Philox4x32-10 words for counters c0 .. c0+count-1 of (seed, stream): out[4*i + w]. */
 psdproj_status psdproj_philox_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count,
                                     uint32_t* out_dev, psdproj_stream_t stream);
+/* The n x r structured test matrix of PSDPROJ_FLAG_SRHT for key seed, as double, column-major
+ * (entry (i, j) at out_dev[j * n + i]); 1 <= r <= n <= 2^20. */
+psdproj_status psdproj_srht_matrix(uint64_t seed, int64_t n, int32_t r, double* out_dev, psdproj_stream_t stream);
 /* Elements start .. start+count-1 of a Gaussian stream, as double. */
 psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count,
                                 double* out_dev, psdproj_stream_t stream);

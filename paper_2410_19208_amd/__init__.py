@@ -12,7 +12,9 @@ import ctypes
 import os
 
 __all__ = [
-    "PLAIN", "SCALED", "FP64", "FP32", "BF16X3", "Desc", "Result", "Layout", "PsdprojError",
+    "PLAIN", "SCALED", "FLAG_SRHT", "FLAG_CSR", "psdproj_srht_matrix", "psdproj_run_csr", "FP64", "FP32", "BF16X3", "Desc", "Result", "Layout", "PsdprojError", "SdlsDesc",
+    "SdlsInfo", "sdls_desc", "psdproj_sdls_workspace", "psdproj_sdls_solve", "psdproj_exact_workspace",
+    "psdproj_exact",
     "lib", "psdproj_plan", "psdproj_plan_destroy", "psdproj_plan_layout", "psdproj_run", "psdproj_run_static",
     "psdproj_static_scratch_bytes",
     "psdproj_batch_workspace", "psdproj_batch", "psdproj_graph_create", "psdproj_graph_launch",
@@ -23,6 +25,8 @@ __all__ = [
 ]
 
 PLAIN, SCALED = 0, 1
+FLAG_SRHT = 1          # desc.flags: structured (subsampled randomized Hadamard) test matrix
+FLAG_CSR = 2           # desc.flags: sparse A (CSR), run with psdproj_run_csr
 FP64, FP32, BF16X3 = 0, 1, 2
 (OK, E_INVALID, E_ALPHA, E_NONFINITE, E_BREAKDOWN, E_NOMEM, E_BUDGET, E_DEVICE, E_PENDING, E_TIMEOUT,
  E_SCRATCH) = range(11)
@@ -50,6 +54,18 @@ class Layout(ctypes.Structure):
                 ("total", ctypes.c_size_t)]
 
 
+class SdlsDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("q", ctypes.c_int32), ("scal", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("alpha_iters", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("rho", ctypes.c_double), ("beta", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class SdlsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("grad_norm", ctypes.c_double)]
+
+
 class PsdprojError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -74,6 +90,7 @@ _SIGS = {
     "psdproj_plan_destroy": (None, [_vp]),
     "psdproj_plan_layout": (_i32, [_vp, ctypes.POINTER(Layout)]),
     "psdproj_run": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
+    "psdproj_run_csr": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
     "psdproj_run_static": (_i32, [_vp, _vp, _i64, _vp, _i64, _vp, _vp]),
     "psdproj_static_scratch_bytes": (_i32, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "psdproj_batch_workspace": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_sz)]),
@@ -85,6 +102,11 @@ _SIGS = {
     "psdproj_graph_destroy": (None, [_vp]),
     "psdproj_graph_stats": (_i32, [ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "psdproj_tile_override": (_i32, [_i32, _i32]),
+    "psdproj_exact_workspace": (_i32, [_i64, _i32, ctypes.POINTER(_sz)]),
+    "psdproj_exact": (_i32, [_i64, _i32, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp]),
+    "psdproj_sdls_workspace": (_i32, [ctypes.POINTER(SdlsDesc), ctypes.POINTER(_sz)]),
+    "psdproj_sdls_solve": (_i32, [ctypes.POINTER(SdlsDesc), _vp, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp,
+                                  _sz, ctypes.POINTER(SdlsInfo), _vp]),
     "psdproj_server_create": (_i32, [_sz, _i32, ctypes.POINTER(_vp)]),
     "psdproj_submit": (_i32, [_vp, ctypes.POINTER(Desc), _vp, _i64, _vp, _i64, ctypes.POINTER(_u64)]),
     "psdproj_poll": (_i32, [_vp, _u64, ctypes.POINTER(Result)]),
@@ -93,6 +115,7 @@ _SIGS = {
     "psdproj_server_destroy": (None, [_vp]),
     "psdproj_philox_words": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
     "psdproj_gaussian": (_i32, [_u64, _u32, _u64, _i64, _vp, _vp]),
+    "psdproj_srht_matrix": (_i32, [_u64, _i64, _i32, _vp, _vp]),
     "psdproj_profile_enable": (_i32, [_i32]),
     "psdproj_profile_select": (_i32, [ctypes.c_uint64]),
     "psdproj_profile_reset": (_i32, []),
@@ -143,6 +166,10 @@ def psdproj_kernel_name(kind: int) -> str:
     return lib.psdproj_kernel_name(kind).decode()
 
 
+def psdproj_srht_matrix(seed, n, r, out_dev, stream=0) -> None:
+    _check(lib.psdproj_srht_matrix(seed, n, r, out_dev, stream), "psdproj_srht_matrix")
+
+
 def psdproj_status_str(status: int) -> str:
     return lib.psdproj_status_str(int(status)).decode()
 
@@ -178,6 +205,12 @@ def psdproj_plan_layout(plan) -> Layout:
 def psdproj_run(plan, A, lda, P, ldp, workspace, result_dev, stream=0) -> None:
     """All pointers are device addresses (ints); stream is a hipStream_t handle (int)."""
     _check(lib.psdproj_run(plan, A, lda, P, ldp, workspace, result_dev, stream), "psdproj_run")
+
+
+def psdproj_run_csr(plan, row_ptr, col_idx, vals, nnz, P, ldp, workspace, result_dev, stream=0) -> None:
+    """One projection of a sparse A (CSR, both triangles) planned with FLAG_CSR."""
+    _check(lib.psdproj_run_csr(plan, row_ptr, col_idx, vals, nnz, P, ldp, workspace, result_dev, stream),
+           "psdproj_run_csr")
 
 
 def psdproj_run_static(plan, A, lda, P, ldp, result_dev, stream=0) -> None:
@@ -234,6 +267,38 @@ def psdproj_graph_stats():
 def psdproj_tile_override(precision, split) -> None:
     """Plans created afterwards with `precision` use pass split-K `split` (0: the tuned table)."""
     _check(lib.psdproj_tile_override(int(precision), int(split)), "psdproj_tile_override")
+
+
+def psdproj_exact_workspace(n, precision) -> int:
+    out = _sz()
+    _check(lib.psdproj_exact_workspace(n, precision, ctypes.byref(out)), "psdproj_exact_workspace")
+    return out.value
+
+
+def psdproj_exact(n, precision, A, lda, P, ldp, workspace, workspace_bytes, result_dev, stream=0) -> None:
+    """The exact projection (Thm 1) of the n x n matrix at A into P."""
+    _check(lib.psdproj_exact(n, precision, A, lda, P, ldp, workspace, workspace_bytes, result_dev, stream),
+           "psdproj_exact")
+
+
+def sdls_desc(n, m, k=0, p=0, q=0, scal=0, precision=FP64, alpha_iters=10, max_iters=100, rho=1.0, beta=0.5,
+              eps=1e-10, seed=0) -> SdlsDesc:
+    return SdlsDesc(n, m, k, p, q, scal, precision, alpha_iters, max_iters, 0, rho, beta, eps, seed)
+
+
+def psdproj_sdls_workspace(desc: SdlsDesc) -> int:
+    out = _sz()
+    _check(lib.psdproj_sdls_workspace(ctypes.byref(desc), ctypes.byref(out)), "psdproj_sdls_workspace")
+    return out.value
+
+
+def psdproj_sdls_solve(desc: SdlsDesc, C, ldc, A, lda, a_stride, b_dev, y_dev, X, ldx, workspace, workspace_bytes,
+                       stream=0) -> SdlsInfo:
+    """Alg. 6 on device buffers (pointers); returns the host info record."""
+    info = SdlsInfo()
+    _check(lib.psdproj_sdls_solve(ctypes.byref(desc), C, ldc, A, lda, a_stride, b_dev, y_dev, X, ldx, workspace,
+                                  workspace_bytes, ctypes.byref(info), stream), "psdproj_sdls_solve")
+    return info
 
 
 def psdproj_server_create(hbm_budget_bytes, max_inflight):

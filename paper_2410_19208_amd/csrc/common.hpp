@@ -67,8 +67,14 @@ struct Prob {
   int32_t ngchunk, alpha_iters;    // Gram row chunks, N of Alg. 4/5
   int32_t alpha_mode, rwpad;       // 0: alpha given (or plain), 1: estimate; rebuild-factor row stride
   int32_t npass_tiles, avec;       // avec: rows of A start and end 16-byte aligned (vector loads)
-  int32_t ktail, pad0;             // BF16X3 16-byte path: K rows ktail .. n-1 (n mod 32 of them)
-                                   // are added by the pass reduction, not the pass (else n)
+  int32_t ktail, sketch;           // BF16X3 16-byte path: K rows ktail .. n-1 (n mod 32 of them)
+                                   // are added by the pass reduction, not the pass (else n);
+                                   // sketch: 0 Gaussian test matrix, 1 structured (+-1 Hadamard)
+  int32_t srht_m, csr;             // structured sketch: transform size 2^srht_m >= n; csr: A is
+                                   // sparse (CSR, both triangles), A points to its values
+  const int32_t* rowptr;           // CSR row starts (n + 1) and column indices
+  const int32_t* colidx;
+  void* zr;                        // CSR passes: the pass operand row-major (n x rpad)
   uint64_t seed;
   double alpha_in;
   const void* A; int64_t lda;

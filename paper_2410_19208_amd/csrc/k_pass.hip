@@ -608,6 +608,7 @@ __global__ __launch_bounds__(RD_THREADS) void k_pass_reduce(const Prob* __restri
 
 // ---------------------------------------------------------------- tile counts and launchers
 int tiles_pass(const Prob& p) {
+  if (p.csr) return (p.n + 31) / 32;   // k_spmm: 32 rows per workgroup
   const int bm = (p.prec == F64) ? PASS_BM_D : PASS_BM_F;
   return ((p.n + bm - 1) / bm) * p.split;
 }

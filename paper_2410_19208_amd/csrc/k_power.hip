@@ -79,16 +79,17 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv_finish(const Prob* __rest
   const int x = threadIdx.x;
   const int row = b * GEMV_TILE + x;
   const gmem<const double>* __restrict__ part = gp((const double*)p.gvp) + (int64_t)b * nb * GEMV_TILE;
+  const int ncontrib = p.csr ? 1 : nb;   // a sparse product gives one contribution per row
   double y = 0.0;
   if (row < n) {
     double s = 0.0;
-    for (int c0 = 0; c0 < nb; c0 += FIN_CHUNK) {
+    for (int c0 = 0; c0 < ncontrib; c0 += FIN_CHUNK) {
       double t[FIN_CHUNK];
 #pragma unroll
-      for (int k = 0; k < FIN_CHUNK; ++k) t[k] = part[(int64_t)min(c0 + k, nb - 1) * GEMV_TILE + x];
+      for (int k = 0; k < FIN_CHUNK; ++k) t[k] = part[(int64_t)min(c0 + k, ncontrib - 1) * GEMV_TILE + x];
 #pragma unroll
       for (int k = 0; k < FIN_CHUNK; ++k)
-        if (c0 + k < nb) s += t[k];
+        if (c0 + k < ncontrib) s += t[k];
     }
     y = s - shift * (vin[row] * inv);
     vout[row] = y;
@@ -245,11 +246,42 @@ __device__ __forceinline__ void gemv_tile(const Prob& p, int t) {
   }
 }
 
+// Sparse A (CSR, both triangles): block row b, one row per thread, y_i = sum_k a_ik v_k in FP64 over
+// the row's nonzeros in storage order; the row's one contribution goes to slot 0 of its partials.
+// Indices outside [0, n) or [0, nnz) are skipped and set E_INVALID (nnz travels in lda).
+template <typename T>
+__device__ __forceinline__ void spmv_rows(const Prob& p, int b) {
+  const int n = p.n, ld = p.ld, nb = (n + GEMV_TILE - 1) / GEMV_TILE;
+  const int pp = p.iscal[I_PP] & 1;
+  const gmem<const double>* __restrict__ vin = gp((const double*)p.vec) + (int64_t)pp * ld;
+  const double inv = p.scal[S_INV];
+  const int i = b * GEMV_TILE + threadIdx.x;
+  if (i >= n) return;
+  const gmem<const int32_t>* rowptr = gp(p.rowptr);
+  const gmem<const int32_t>* colidx = gp(p.colidx);
+  const gmem<const T>* vals = gp((const T*)p.A);
+  const int64_t k0 = max((int64_t)rowptr[i], (int64_t)0), k1 = min((int64_t)rowptr[i + 1], p.lda);
+  double y = 0.0;
+  bool bad = false;
+  for (int64_t k = k0; k < k1; ++k) {
+    const int j = colidx[k];
+    if ((unsigned)j >= (unsigned)n) { bad = true; continue; }
+    y = fma((double)vals[k], vin[j] * inv, y);
+  }
+  if (bad) set_status(p, PSDPROJ_E_INVALID);
+  gp(p.gvp)[(int64_t)b * nb * GEMV_TILE + threadIdx.x] = y;
+}
+
 __global__ __launch_bounds__(GEMV_THREADS) void k_gemv(const Prob* __restrict__ probs, const int* __restrict__ tstart,
                                                        int nprob) {
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int t = blockIdx.x - tstart[pi];
+  if (p.csr) {
+    if (p.prec == F64) spmv_rows<double>(p, t);
+    else spmv_rows<float>(p, t);
+    return;
+  }
   if (p.prec == F64) gemv_tile<double, 4>(p, t);
   else gemv_tile<float, 8>(p, t);
 }
@@ -289,7 +321,7 @@ __global__ void k_finalize(const Prob* __restrict__ probs, const int* __restrict
 
 int tiles_gemv(const Prob& p) {
   const int nb = (p.n + GEMV_TILE - 1) / GEMV_TILE;
-  return nb * (nb + 1) / 2;
+  return p.csr ? nb : nb * (nb + 1) / 2;
 }
 int tiles_gemv_rows(const Prob& p) { return (p.n + GEMV_TILE - 1) / GEMV_TILE; }
 int tiles_vec(const Prob& p) { return (p.ld + 1023) / 1024; }

@@ -48,6 +48,38 @@ __device__ __forceinline__ double gauss_at(uint64_t seed, uint32_t stream, uint6
   return (g & 1) ? rad * sin(ang) : rad * cos(ang);
 }
 
+// Structured test matrix (the subsampled randomized Hadamard transform, the structured
+// alternative of Sec. 3.1's footnote), entries +1 / -1:
+//   Omega[i][j] = d_i (-1)^popcount(i & s_j),  d_i from the low bit of word x0 of counter i,
+//   stream 3, and s_j = pi(j) for a permutation pi of [0, 2^m) (m = max(1, ceil(log2 n))): a
+//   four-round Feistel network on w = m + (m mod 2) bits, round t adding F_t(R) = low w/2 bits of
+//   word x0 of counter t 2^(w/2) + R (stream 4) into the left half, re-applied while the value is
+//   at least 2^m (cycle walking keeps it a permutation).
+__device__ __forceinline__ uint32_t feistel(uint64_t seed, uint32_t x, int m) {
+  const int h = (m + (m & 1)) >> 1;
+  const uint32_t mask = (1u << h) - 1u;
+  uint32_t L = (x >> h) & mask, R = x & mask;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint32_t f = philox_at(seed, 4u, ((uint64_t)t << h) + R).x & mask;
+    const uint32_t nl = R;
+    R = L ^ f;
+    L = nl;
+  }
+  return (L << h) | R;
+}
+
+__device__ __forceinline__ uint32_t srht_column(uint64_t seed, uint32_t j, int m) {
+  uint32_t y = feistel(seed, j, m);
+  while (y >= (1u << m)) y = feistel(seed, y, m);   // ends: the walk follows a cycle through j
+  return y;
+}
+
+__device__ __forceinline__ double srht_at(uint64_t seed, int i, uint32_t s) {
+  const double d = (philox_at(seed, 3u, (uint64_t)i).x & 1u) ? -1.0 : 1.0;
+  return (__builtin_popcount((uint32_t)i & s) & 1) ? -d : d;
+}
+
 __device__ __forceinline__ void split_bf16(float x, bf16& hi, bf16& lo) {
   hi = (bf16)x;
   lo = (bf16)(x - (float)hi);
@@ -65,7 +97,9 @@ __global__ __launch_bounds__(256) void k_omega(const Prob* __restrict__ probs, c
     if (idx >= total) break;
     const int j = (int)(idx / p.ld), i = (int)(idx % p.ld);
     double v = 0.0;
-    if (i < p.n && j < p.r) v = gauss_at(p.seed, 0u, (uint64_t)j * (uint64_t)p.n + (uint64_t)i);
+    if (i < p.n && j < p.r)
+      v = p.sketch ? srht_at(p.seed, i, srht_column(p.seed, (uint32_t)j, p.srht_m))
+                   : gauss_at(p.seed, 0u, (uint64_t)j * (uint64_t)p.n + (uint64_t)i);
     if (p.prec == F64) {
       ((double*)p.zm)[idx] = v;
     } else {
@@ -114,6 +148,14 @@ __global__ void k_gauss(uint64_t seed, uint32_t stream, uint64_t start, int64_t 
   out[i] = gauss_at(seed, stream, start + (uint64_t)i);
 }
 
+// the n x r structured test matrix, column-major (entry (i, j) at out[j n + i])
+__global__ void k_srht(uint64_t seed, int n, int r, int m, double* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * r) return;
+  const int j = (int)(e / n), i = (int)(e - (int64_t)j * n);
+  out[e] = srht_at(seed, i, srht_column(seed, (uint32_t)j, m));
+}
+
 // ---------------------------------------------------------------- launchers
 void launch_omega(const Launch& L) {
   hipLaunchKernelGGL(k_omega, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob);
@@ -128,6 +170,14 @@ void launch_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count,
 void launch_gauss(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count, double* out, hipStream_t s) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_gauss, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, seed, stream_id, start, count, out);
+}
+
+void launch_srht(uint64_t seed, int n, int r, double* out, hipStream_t s) {
+  int m = 1;
+  while ((int64_t(1) << m) < n) ++m;
+  const int64_t count = (int64_t)n * r;
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_srht, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, seed, n, r, m, out);
 }
 
 }  // namespace psd

@@ -32,11 +32,16 @@ void launch_omega(const Launch& L);
 void launch_power_init(const Launch& L, int which);
 void launch_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count, uint32_t* out, hipStream_t s);
 void launch_gauss(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count, double* out, hipStream_t s);
+void launch_srht(uint64_t seed, int n, int r, double* out, hipStream_t s);
 
 // Passes over A: part[s] = A[:, chunk s] * Z[chunk s, :]; reduce: Y = sum_s part[s]
 // (+ scaled epilogue (Y + alpha Z)/alpha).
 void launch_pass(const Launch& L, int prec, int ncb);
 void launch_pass_reduce(const Launch& L);
+// CSR operand: Z to row-major (k_zt), then the sparse pass (k_spmm, one partial, no split)
+int tiles_zt(const Prob& p);
+void launch_zt(const Launch& L);
+void launch_spmm(const Launch& L);
 void pass_init();                     // dynamic-LDS attributes of the pass kernels
 
 // Gram X^T Y (mode 0: Y^T Y of the pass output, upper tiles; 1: Q1^T Q1; 2: Q^T Y full,

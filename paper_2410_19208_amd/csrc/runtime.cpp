@@ -60,7 +60,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   if (d->q < 0 || d->q > 16) return PSDPROJ_E_INVALID;
   if (d->variant != PSDPROJ_PLAIN && d->variant != PSDPROJ_SCALED) return PSDPROJ_E_INVALID;
   if (d->precision < PSDPROJ_FP64 || d->precision > PSDPROJ_BF16X3) return PSDPROJ_E_INVALID;
-  if (d->flags != 0) return PSDPROJ_E_INVALID;
+  if ((d->flags & ~(uint32_t)(PSDPROJ_FLAG_SRHT | PSDPROJ_FLAG_CSR)) != 0) return PSDPROJ_E_INVALID;
   int alpha_mode = 0;
   if (d->variant == PSDPROJ_SCALED) {
     if (std::isnan(d->alpha) || std::isinf(d->alpha)) return PSDPROJ_E_INVALID;
@@ -78,6 +78,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.es = (pl.prec == F64) ? 8 : 4;
   pl.ncb = pl.rpad / 16;
   pl.alpha_mode = alpha_mode;
+  pl.csr = (d->flags & PSDPROJ_FLAG_CSR) ? 1 : 0;
   // split-K, at most 8 (one K chunk per XCD).  FP64: enough workgroups to fill 256 CUs twice.
   // FP32 / BF16X3 (one 8-wave workgroup per CU): 8 chunks of at least 64 columns, so each
   // XCD's L2 holds one chunk of the panel.
@@ -88,6 +89,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
                                : std::min(8, std::max(1, (n + 63) / 64));
   const int tuned = tuned_split(pl.prec, n, pl.rpad);
   if (tuned > 0) split = std::min(tuned, MAX_SPLIT);
+  if (pl.csr) split = 1;   // the sparse pass has no K chunks
   int kchunk = rup((n + split - 1) / split, bk);
   split = (n + kchunk - 1) / kchunk;
   pl.split = split;
@@ -128,6 +130,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.o_scal = take(NSCAL * 8);
   pl.o_iscal = take(NISCAL * 4);
   pl.o_drop = take(PSDPROJ_MAX_RANK * 4);
+  pl.o_zr = pl.csr ? take((size_t)n * pl.rpad * pl.es) : 0;
   pl.region = o;
   // schedule and header of a single run
   const Plan* one = &pl;
@@ -137,7 +140,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
 }
 
 Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda, void* P, int64_t ldp,
-               psdproj_result* res) {
+               psdproj_result* res, const Csr* csr) {
   Prob p;
   std::memset(&p, 0, sizeof(p));
   const psdproj_desc& d = pl.d;
@@ -154,6 +157,17 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   // are added by the pass reduction (n < 32: the element path)
   if (pl.prec == B3 && d.n < 32) p.avec = 0;
   p.ktail = (pl.prec == B3 && p.avec) ? (int)(d.n - d.n % 32) : (int)d.n;
+  p.sketch = (d.flags & PSDPROJ_FLAG_SRHT) ? 1 : 0;
+  p.csr = pl.csr;
+  if (pl.csr) {
+    p.avec = 0;
+    p.ktail = (int)d.n;
+    p.rowptr = csr ? csr->rowptr : nullptr;
+    p.colidx = csr ? csr->colidx : nullptr;
+    p.zr = region ? (void*)(region + pl.o_zr) : nullptr;
+  }
+  p.srht_m = 1;
+  while ((int64_t(1) << p.srht_m) < d.n) ++p.srht_m;
   auto at = [&](size_t off) { return (void*)(region + off); };
   p.zm = at(pl.o_zm);
   p.zhi = (bf16*)(pl.prec == B3 ? at(pl.o_zhi) : nullptr);
@@ -196,7 +210,8 @@ static int stage_tiles(const Prob& p, int kind) {
     case K_PINIT: return tiles_vec(p);
     case K_GEMV: return tiles_gemv(p);
     case K_GEMV_FIN: return tiles_gemv_rows(p);
-    case K_PASS: return rup(tiles_pass(p), 8);
+    case K_PASS: return p.csr ? tiles_pass(p) : rup(tiles_pass(p), 8);
+    case K_ZT: return p.csr ? tiles_zt(p) : 0;
     case K_PRED: return tiles_reduce(p);
     case K_GRAM_SYM: return tiles_gram(p, false);
     case K_GRAM_FULL: return tiles_gram(p, true);
@@ -228,6 +243,7 @@ static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
   // o: position of the orthonormalisation in each problem's sequence (see orth_single)
   auto orth = [&](int when, int iter, int o) {
     const int a0 = 0 + 16 * (o + 1), a1 = 1 + 16 * (o + 1);
+    add(K_ZT, 0, when, iter);
     add(K_PASS, 0, when, iter);
     add(K_PRED, 0, when, iter);
     add(K_GRAM_SYM, a0, when, iter);
@@ -244,6 +260,7 @@ static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
     orth(W_POWER, it, 1 + 2 * it);
     orth(W_POWER, it, 2 + 2 * it);
   }
+  add(K_ZT, 0, W_ALL, 0);
   add(K_PASS, 0, W_ALL, 0);
   add(K_PRED, 0, W_ALL, 0);
   add(K_GRAM_FULL, 2, W_ALL, 0);
@@ -260,17 +277,19 @@ static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
 void build_schedule(const Plan* const* plans, int count, Schedule& s) {
   s.order.resize(count);
   for (int i = 0; i < count; ++i) s.order[i] = i;
+  // pass and rebuild kernels are grouped by (precision, column blocks); a CSR operand takes
+  // the sparse pass, so it is a key of its own (precision + 8)
+  auto gkey = [&](int i) { return plans[i]->prec + 8 * plans[i]->csr; };
   std::stable_sort(s.order.begin(), s.order.end(), [&](int a, int b) {
-    if (plans[a]->prec != plans[b]->prec) return plans[a]->prec < plans[b]->prec;
+    if (gkey(a) != gkey(b)) return gkey(a) < gkey(b);
     return plans[a]->ncb < plans[b]->ncb;
   });
-  // groups of equal (prec, ncb), as ranges of the sorted order
+  // groups of equal (key, ncb), as ranges of the sorted order
   s.groups.clear();
   for (int i = 0; i < count;) {
     int j = i;
-    while (j < count && plans[s.order[j]]->prec == plans[s.order[i]]->prec &&
-           plans[s.order[j]]->ncb == plans[s.order[i]]->ncb) ++j;
-    s.groups.push_back({i, j - i, plans[s.order[i]]->prec, plans[s.order[i]]->ncb});
+    while (j < count && gkey(s.order[j]) == gkey(s.order[i]) && plans[s.order[j]]->ncb == plans[s.order[i]]->ncb) ++j;
+    s.groups.push_back({i, j - i, gkey(s.order[i]), plans[s.order[i]]->ncb});
     i = j;
   }
   int max_iters = 0, max_q = 0;
@@ -402,6 +421,23 @@ struct Prof {
 Prof& prof() { static Prof P; return P; }
 }  // namespace
 
+ProfScope::ProfScope(int k, hipStream_t s) : kind(k), stream(s) {
+  Prof& PR = prof();
+  std::lock_guard<std::mutex> g(PR.mu);
+  if (!PR.on || !((PR.kinds >> kind) & 1ull)) return;
+  a = PR.get();
+  b = PR.get();
+  if (a) hipEventRecord(a, stream);
+}
+
+ProfScope::~ProfScope() {
+  if (!a || !b) return;
+  hipEventRecord(b, stream);
+  Prof& PR = prof();
+  std::lock_guard<std::mutex> g(PR.mu);
+  PR.pending.push_back({kind, a, b});
+}
+
 // Enqueue every launch of a schedule whose header (Prob array + tile tables) is at `hdr`.
 psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream, bool allow_timing) {
   kernel_init_once();
@@ -434,7 +470,8 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
       case K_GEMV: launch_gemv(L, R.arg); break;
       case K_GEMV_FIN: launch_gemv_finish(L, R.arg); break;
       case K_ALPHA: launch_alpha(L); break;
-      case K_PASS: launch_pass(L, R.prec, R.ncb); break;
+      case K_PASS: (R.prec >= 8) ? launch_spmm(L) : launch_pass(L, R.prec, R.ncb); break;
+      case K_ZT: launch_zt(L); break;
       case K_PRED: launch_pass_reduce(L); break;
       case K_GRAM_SYM: case K_GRAM_FULL: launch_gram(L, R.arg); break;
       case K_GRED: launch_gram_reduce(L, R.arg); break;
@@ -444,7 +481,7 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
       case K_BISECT: launch_bisect(L); break;
       case K_INVIT: launch_invit(L); break;
       case K_BACKXF: launch_backxf(L); break;
-      case K_REBUILD: launch_rebuild(L, R.prec); break;
+      case K_REBUILD: launch_rebuild(L, R.prec & 7); break;
       case K_FINAL: launch_finalize(L); break;
     }
     if (hipGetLastError() != hipSuccess) return PSDPROJ_E_DEVICE;
@@ -461,7 +498,8 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
 static const char* const KIND_NAMES[K_NKINDS] = {
     "k_setup", "k_omega", "k_power_init", "k_gemv", "k_alpha", "k_pass", "k_pass_reduce", "k_gram",
     "k_gram_full", "k_gram_reduce", "k_chol", "k_apply", "k_tridiag", "k_bisect", "k_invit", "k_rebuild",
-    "k_finalize", "k_gemv_finish", "k_apply_factor", "k_backxf"};
+    "k_finalize", "k_gemv_finish", "k_apply_factor", "k_backxf", "k_zt", "k_sdls_form", "k_sdls_trace",
+    "k_sdls_update", "k_gemm64", "k_exact_misc"};
 
 // ------------------------------------------------------------------------------ HIP graphs
 // A schedule's launches reach the problems only through the header at `hdr` (each kernel
@@ -605,6 +643,7 @@ psdproj_status launch_schedule(const Schedule& s, unsigned char* hdr, hipStream_
 
 psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp) {
   const int64_t n = pl.d.n;
+  if (pl.csr) return PSDPROJ_E_INVALID;   // a sparse operand goes through psdproj_run_csr
   if (!A || !P) return PSDPROJ_E_INVALID;
   if (lda < n || ldp < n) return PSDPROJ_E_INVALID;
   if (((uintptr_t)A & 15) || ((uintptr_t)P & 15)) return PSDPROJ_E_INVALID;
@@ -617,7 +656,8 @@ psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const 
 
 psdproj_status make_header(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
                            void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
-                           psdproj_result* results, Schedule& s, std::vector<unsigned char>& host) {
+                           psdproj_result* results, Schedule& s, std::vector<unsigned char>& host,
+                           const Csr* csr = nullptr) {
   build_schedule(plans, count, s);
   size_t need = s.header_bytes;
   for (int i = 0; i < count; ++i) need += plans[i]->region;
@@ -630,7 +670,7 @@ psdproj_status make_header(int count, const Plan* const* plans, const void* cons
   for (int i = 0; i < count; ++i) { roff[i] = o; o += plans[i]->region; }
   for (int k = 0; k < count; ++k) {
     const int i = s.order[k];
-    hp[k] = make_prob(*plans[i], ws + roff[i], A[i], lda[i], P[i], ldp[i], results + i);
+    hp[k] = make_prob(*plans[i], ws + roff[i], A[i], lda[i], P[i], ldp[i], results + i, csr ? csr + i : nullptr);
   }
   std::memcpy(host.data() + s.prob_bytes, s.tdata.data(), s.tdata.size() * sizeof(int));
   return PSDPROJ_OK;
@@ -638,10 +678,10 @@ psdproj_status make_header(int count, const Plan* const* plans, const void* cons
 
 psdproj_status run_group(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
                          void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
-                         psdproj_result* results, hipStream_t stream) {
+                         psdproj_result* results, hipStream_t stream, const Csr* csr) {
   Schedule s;
   std::vector<unsigned char> host;
-  psdproj_status st = make_header(count, plans, A, lda, P, ldp, ws, ws_bytes, results, s, host);
+  psdproj_status st = make_header(count, plans, A, lda, P, ldp, ws, ws_bytes, results, s, host, csr);
   if (st != PSDPROJ_OK) return st;
   st = upload(ws, host.data(), s.header_bytes, stream);
   if (st != PSDPROJ_OK) return st;
@@ -758,6 +798,21 @@ psdproj_status psdproj_run(psdproj_plan_t plan, const void* A, int64_t lda, void
   if (st != PSDPROJ_OK) return st;
   return run_group(1, &pl, &A, &lda, &P, &ldp, (unsigned char*)workspace, pl->header_single + pl->region,
                    result_dev, (hipStream_t)stream);
+}
+
+psdproj_status psdproj_run_csr(psdproj_plan_t plan, const int32_t* row_ptr, const int32_t* col_idx, const void* vals,
+                               int64_t nnz, void* P, int64_t ldp, void* workspace, psdproj_result* result_dev,
+                               psdproj_stream_t stream) {
+  if (!plan || !row_ptr || !col_idx || !vals || !P || !workspace || !result_dev || nnz < 0) return PSDPROJ_E_INVALID;
+  const Plan* pl = (const Plan*)plan;
+  if (!pl->csr || ldp < pl->d.n || ((uintptr_t)P & 15) || ((uintptr_t)workspace & 255)) return PSDPROJ_E_INVALID;
+  if (P == vals) return PSDPROJ_E_INVALID;
+  const Csr c{row_ptr, col_idx};
+  const void* Av = vals;
+  void* Pv = P;
+  const int64_t lda = nnz;   // the descriptor carries nnz in lda for a sparse operand
+  return run_group(1, &pl, &Av, &lda, &Pv, &ldp, (unsigned char*)workspace, pl->header_single + pl->region,
+                   result_dev, (hipStream_t)stream, &c);
 }
 
 psdproj_status psdproj_run_static(psdproj_plan_t plan, const void* A, int64_t lda, void* P, int64_t ldp,
@@ -882,6 +937,12 @@ psdproj_status psdproj_gaussian(uint64_t seed, uint32_t stream_id, uint64_t star
                                 psdproj_stream_t stream) {
   if (count < 0 || (count > 0 && !out_dev)) return PSDPROJ_E_INVALID;
   launch_gauss(seed, stream_id, start, count, out_dev, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_E_DEVICE;
+}
+
+psdproj_status psdproj_srht_matrix(uint64_t seed, int64_t n, int32_t r, double* out_dev, psdproj_stream_t stream) {
+  if (n < 1 || n > (1 << 20) || r < 1 || r > n || !out_dev) return PSDPROJ_E_INVALID;
+  launch_srht(seed, (int)n, r, out_dev, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? PSDPROJ_OK : PSDPROJ_E_DEVICE;
 }
 

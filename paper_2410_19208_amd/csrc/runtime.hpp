@@ -10,7 +10,8 @@ namespace psd {
 
 enum Kind {
   K_SETUP, K_OMEGA, K_PINIT, K_GEMV, K_ALPHA, K_PASS, K_PRED, K_GRAM_SYM, K_GRAM_FULL, K_GRED,
-  K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_GEMV_FIN, K_FACTOR, K_BACKXF, K_NKINDS
+  K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_GEMV_FIN, K_FACTOR, K_BACKXF, K_ZT,
+  K_SDLS_FORM, K_SDLS_TRACE, K_SDLS_UPDATE, K_GEMM64, K_EXACT_MISC, K_NKINDS
 };
 enum When { W_ALL, W_ALPHA, W_ALPHA_ITER, W_POWER };
 
@@ -34,25 +35,36 @@ struct Schedule {
 // An immutable, validated problem description with its tiling and workspace layout.
 struct Plan {
   psdproj_desc d;
-  int r, rpad, ld, prec, es, ncb, alpha_mode;
+  int r, rpad, ld, prec, es, ncb, alpha_mode, csr;
   int split, kchunk, ngchunk, rwpad;
   size_t region;          // workspace bytes of the problem's own buffers
   size_t header_single;   // header bytes of a single run
   size_t o_zm, o_zhi, o_zlo, o_y, o_part, o_q1, o_wf, o_whi, o_wlo, o_gpart;
   size_t o_G, o_F, o_C, o_H, o_V, o_xt, o_evals, o_tau, o_td, o_te, o_wts;
-  size_t o_vec, o_vpart, o_gvp, o_scal, o_iscal, o_drop;
+  size_t o_vec, o_vpart, o_gvp, o_scal, o_iscal, o_drop, o_zr;
   Schedule single;        // launch schedule of a single run (header_single bytes of header)
 };
 
 psdproj_status make_plan(const psdproj_desc* d, Plan& pl);
+// A sparse operand (CSR, both triangles of the symmetric matrix): row starts and column indices
+struct Csr { const int32_t* rowptr; const int32_t* colidx; };
 Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda, void* P, int64_t ldp,
-               psdproj_result* res);
+               psdproj_result* res, const Csr* csr = nullptr);
 void build_schedule(const Plan* const* plans, int count, Schedule& s);
 psdproj_status upload(void* dst, const void* src, size_t bytes, hipStream_t stream);
 psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream, bool allow_timing = true);
+// Kernel timing of a launch made outside a schedule (the SDLS and exact-projection kernels):
+// while timing is enabled for `kind`, the scope brackets the launches it encloses with events.
+struct ProfScope {
+  ProfScope(int kind, hipStream_t stream);
+  ~ProfScope();
+  int kind;
+  hipStream_t stream;
+  hipEvent_t a = nullptr, b = nullptr;
+};
 psdproj_status check_operands(const Plan& pl, const void* A, int64_t lda, const void* P, int64_t ldp);
 psdproj_status run_group(int count, const Plan* const* plans, const void* const* A, const int64_t* lda,
                          void* const* P, const int64_t* ldp, unsigned char* ws, size_t ws_bytes,
-                         psdproj_result* results, hipStream_t stream);
+                         psdproj_result* results, hipStream_t stream, const Csr* csr = nullptr);
 
 }  // namespace psd

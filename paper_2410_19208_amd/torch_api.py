@@ -9,12 +9,13 @@ import ctypes
 
 import torch
 
-from . import (BF16X3, FP32, FP64, PLAIN, SCALED, Layout, Result, psdproj_batch, psdproj_batch_workspace,
+from . import (BF16X3, FLAG_CSR, FLAG_SRHT, FP32, FP64, PLAIN, SCALED, Layout, Result, psdproj_batch, psdproj_batch_workspace,
+               psdproj_exact, psdproj_exact_workspace, psdproj_run_csr, psdproj_sdls_solve, psdproj_sdls_workspace, sdls_desc,
                psdproj_plan, psdproj_plan_destroy, psdproj_plan_layout, psdproj_poll, psdproj_run,
                psdproj_server_create, psdproj_server_destroy, psdproj_server_times, psdproj_submit, psdproj_wait)
 
-__all__ = ["Projector", "BatchProjector", "Server", "stream_handle", "read_results", "PRECISIONS", "VARIANTS",
-           "storage_dtype"]
+__all__ = ["Projector", "SparseProjector", "BatchProjector", "Server", "SdlsSolver", "ExactProjector", "stream_handle", "read_results", "PRECISIONS",
+           "VARIANTS", "storage_dtype"]
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 VARIANTS = {"plain": PLAIN, "scaled": SCALED}
@@ -39,11 +40,13 @@ class Projector:
     """One plan with its own workspace and result buffers on `device`."""
 
     def __init__(self, n, k, p, q=0, variant="plain", precision="bf16x3", seed=0, alpha=0.0,
-                 alpha_iters=10, device="cuda"):
+                 alpha_iters=10, device="cuda", sketch="gaussian"):
         self.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.n = int(n)
-        self.plan, self.ws_bytes = psdproj_plan(n, k, p, q, self.variant, self.precision, seed, alpha, alpha_iters)
+        flags = {"gaussian": 0, "srht": FLAG_SRHT}[sketch]
+        self.plan, self.ws_bytes = psdproj_plan(n, k, p, q, self.variant, self.precision, seed, alpha, alpha_iters,
+                                                flags)
         self.layout: Layout = psdproj_plan_layout(self.plan)
         self.device = torch.device(device)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -205,3 +208,97 @@ class Server:
     def __del__(self):
         self.close()
 
+
+class SdlsSolver:
+    """Alg. 6 (dual gradient descent for the SDLS problem) through psdproj_sdls_solve.
+
+    scal: -1 exact projection, 0 Alg. 2, 1 Alg. 3 (alpha by Alg. 5).  C (n x n), A (m x n x n) and
+    b (m) are device tensors (C and A in the precision's storage dtype, b float64); solve(y0)
+    returns (y, X, info) with X the last projection."""
+
+    def __init__(self, n, m, k=0, p=0, q=0, scal=0, precision="fp64", alpha_iters=10, max_iters=100, rho=1.0,
+                 beta=0.5, eps=1e-10, seed=0, device="cuda"):
+        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.desc = sdls_desc(n, m, k, p, q, scal, pr, alpha_iters, max_iters, rho, beta, eps, seed)
+        self.n, self.m = int(n), int(m)
+        self.dtype = storage_dtype(pr)
+        self.device = torch.device(device)
+        self.ws_bytes = psdproj_sdls_workspace(self.desc)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def solve(self, C, A, b, y0, X=None, stream=None):
+        n, m = self.n, self.m
+        if C.shape != (n, n) or A.shape != (m, n, n) or C.dtype != self.dtype or A.dtype != self.dtype:
+            raise ValueError("C must be n x n and A m x n x n in the storage dtype")
+        if not (C.is_contiguous() and A.is_contiguous()):
+            raise ValueError("C and A must be contiguous")
+        y = y0.to(device=self.device, dtype=torch.float64).clone()
+        bb = b.to(device=self.device, dtype=torch.float64).contiguous()
+        if X is None:
+            X = torch.empty((n, n), dtype=self.dtype, device=self.device)
+        info = psdproj_sdls_solve(self.desc, C.data_ptr(), C.stride(0), A.data_ptr(), A.stride(1), A.stride(0),
+                                  bb.data_ptr(), y.data_ptr(), X.data_ptr(), X.stride(0), self.workspace.data_ptr(),
+                                  self.ws_bytes, stream_handle(stream))
+        return y, X, info
+
+
+class ExactProjector:
+    """The exact projection (Thm 1) through psdproj_exact, with its own workspace."""
+
+    def __init__(self, n, precision="fp64", device="cuda"):
+        self.n = int(n)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.dtype = storage_dtype(self.precision)
+        self.device = torch.device(device)
+        self.ws_bytes = psdproj_exact_workspace(self.n, self.precision)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.result_buf = torch.zeros(ctypes.sizeof(Result), dtype=torch.uint8, device=self.device)
+
+    def __call__(self, A, P=None, stream=None):
+        if A.dtype != self.dtype or A.shape != (self.n, self.n) or A.stride(1) != 1:
+            raise ValueError(f"A must be a row-contiguous {self.n}x{self.n} {self.dtype} tensor")
+        if P is None:
+            P = torch.empty_like(A)
+        psdproj_exact(self.n, self.precision, A.data_ptr(), A.stride(0), P.data_ptr(), P.stride(0),
+                      self.workspace.data_ptr(), self.ws_bytes, self.result_buf.data_ptr(), stream_handle(stream))
+        return P
+
+    def result(self) -> Result:
+        return read_results(self.result_buf, 1)[0]
+
+
+class SparseProjector:
+    """One plan for a sparse symmetric A (CSR, both triangles) run through psdproj_run_csr."""
+
+    def __init__(self, n, k, p, q=0, variant="plain", precision="fp32", seed=0, alpha=0.0, alpha_iters=10,
+                 device="cuda"):
+        self.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.n = int(n)
+        self.plan, self.ws_bytes = psdproj_plan(n, k, p, q, self.variant, self.precision, seed, alpha, alpha_iters,
+                                                FLAG_CSR)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.result_buf = torch.zeros(ctypes.sizeof(Result), dtype=torch.uint8, device=self.device)
+        self.dtype = storage_dtype(self.precision)
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan and psdproj_plan_destroy is not None:
+            psdproj_plan_destroy(plan)
+            self.plan = None
+
+    def __call__(self, row_ptr, col_idx, vals, P=None, stream=None):
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32 or vals.dtype != self.dtype:
+            raise ValueError("row_ptr, col_idx int32 and vals in the storage dtype")
+        if row_ptr.numel() != self.n + 1 or col_idx.numel() != vals.numel():
+            raise ValueError("CSR arrays of the wrong size")
+        if P is None:
+            P = torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
+        psdproj_run_csr(self.plan, row_ptr.data_ptr(), col_idx.data_ptr(), vals.data_ptr(), vals.numel(),
+                        P.data_ptr(), P.stride(0), self.workspace.data_ptr(), self.result_buf.data_ptr(),
+                        stream_handle(stream))
+        return P
+
+    def result(self) -> Result:
+        return read_results(self.result_buf, 1)[0]

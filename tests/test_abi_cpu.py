@@ -78,7 +78,7 @@ def plan_status(**kw):
 
 @pytest.mark.parametrize("kw", [
     dict(k=0), dict(p=-1), dict(k=96, p=5), dict(q=-1), dict(q=17), dict(variant=2), dict(precision=3),
-    dict(flags=1), dict(n=0), dict(n=300, k=250, p=10),
+    dict(flags=4), dict(flags=0x80000000), dict(n=0), dict(n=300, k=250, p=10),
     dict(variant=pp.SCALED, alpha=float("nan")), dict(variant=pp.SCALED, alpha=float("inf")),
     dict(variant=pp.SCALED, alpha=0.0, alpha_iters=0), dict(variant=pp.SCALED, alpha=-1.0, alpha_iters=1001),
 ])
@@ -106,7 +106,7 @@ def test_workspace_grows_with_n_and_layout_is_consistent():
         assert L.r == 110 and L.r_pad % 32 == 0 and L.r_pad >= 110
         # a K step of 32 rows starting before n stays inside the panel column
         assert L.panel_ld >= 4000 + 32 and L.panel_ld % 128 == 0
-        assert 1 <= L.split_k <= 8 and L.panel_elem_bytes == 4
+        assert 1 <= L.split_k <= 16 and L.panel_elem_bytes == 4   # split-K from the tuned tile table
         assert L.total == ws
         offs = [L.omega, L.q_panel, L.compressed, L.evals, L.weights, L.factor, L.power_vec]
         assert all(o % 256 == 0 and o < ws for o in offs)
@@ -156,3 +156,39 @@ def test_server_create_without_device_fails_cleanly():
         pp.psdproj_server_create(1 << 20, 4)
     with pytest.raises(pp.PsdprojError):
         pp.psdproj_server_create(16, 4)   # budget below the minimum: E_INVALID
+
+
+def test_tile_table_is_used_by_the_planner():
+    """Every entry of the tuner's table (csrc/tile_table.inc) is a valid split-K for its bucket,
+    and a plan in that bucket takes the table's factor (after the planner's rounding of K chunks
+    to whole 64-row steps); an override wins over the table and 0 restores it."""
+    import re
+    txt = open(os.path.join(ROOT, "paper_2410_19208_amd", "csrc", "tile_table.inc")).read()
+    rows = [tuple(int(x) for x in m.groups()) for m in re.finditer(r"\{(-?\d+), (\d+), (\d+), (\d+)\}", txt)]
+    rows = [r for r in rows if r[0] >= 0]
+    assert rows, "tile table is empty"
+    seen = set()
+    for prec, b, rpad, split in rows:
+        assert (prec, b, rpad) not in seen
+        seen.add((prec, b, rpad))
+        assert prec in (0, 1, 2) and 6 <= b <= 14 and rpad % 32 == 0 and 1 <= split <= 16
+    for prec, b, rpad, split in rows[:: max(1, len(rows) // 25)]:
+        n = 20000 if b == 14 else int(round(2 ** (b + 0.5)))
+        k = rpad - 13
+        if k < 1 or rpad - 3 > n:
+            continue
+        plan, _ = pp.psdproj_plan(n, k, 10, 0, pp.PLAIN, prec)
+        try:
+            L = pp.psdproj_plan_layout(plan)
+            kchunk = -(-(-(-n // split)) // 64) * 64 if prec != 0 else None
+            expect = -(-n // kchunk) if kchunk else split
+            assert L.split_k == expect, (prec, b, rpad, split, L.split_k)
+        finally:
+            pp.psdproj_plan_destroy(plan)
+    pp.psdproj_tile_override(pp.BF16X3, 3)
+    try:
+        plan, _ = pp.psdproj_plan(4096, 100, 10, 0, pp.PLAIN, pp.BF16X3)
+        assert pp.psdproj_plan_layout(plan).split_k == 3
+        pp.psdproj_plan_destroy(plan)
+    finally:
+        pp.psdproj_tile_override(pp.BF16X3, 0)
