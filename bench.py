@@ -94,14 +94,15 @@ def parse():
     ap.add_argument("--sequential", action="store_true",
                     help="time the step as two psdproj_run calls instead of one grouped psdproj_batch")
     ap.add_argument("--mode", default="step",
-                    choices=["step", "batch", "serve", "counters", "exact", "sdls", "sparse", "sketch"],
+                    choices=["step", "batch", "serve", "counters", "exact", "sdls", "sparse", "sketch", "configs"],
                     help="step: the headline n=20000 step (default); batch: 256 uneven problems in one "
                          "grouped launch sequence; serve: Poisson arrivals through the request server; "
                          "counters: a short run for hardware-counter profiles (symmetric Gaussian A, no QR "
                          "in the generator, two grouped steps, then one 1 GiB device copy for calibration); "
                          "exact: the exact projection (Thm 1) against the randomized ones at n=4096; sdls: "
                          "dual gradient descent (Alg. 6) iterations; sparse: the headline step on a sparse A; "
-                         "sketch: the headline step with the structured test matrix")
+                         "sketch: the headline step with the structured test matrix; configs: per-projection "
+                         "times of the small (n=512) and medium (n=4096) workloads with the oracle's beside them")
     ap.add_argument("--qps", default="50,100,200,500,1000,2000", help="serve mode: arrival rates")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests per arrival rate (at most) in serve mode and in the serving leg of the step")
@@ -141,6 +142,8 @@ def main() -> int:
         return run_sparse(args, dev)
     if args.mode == "sketch":
         return run_sketch(args, dev)
+    if args.mode == "configs":
+        return run_configs(args, dev)
     n, k, p, q = args.n, args.k, args.p, args.q
     r = k + p
 
@@ -1015,6 +1018,50 @@ def run_sketch(args, dev) -> int:
     return _step_pair_mode(args, dev, f"large_20k with the structured test matrix: n={n}, k={k}, p={p}, q={q}; "
                                       f"one plain + one scaled projection per step (two runs)",
                            make_pair, bytes_model, "structured subsampled-Hadamard test matrix")
+
+
+def run_configs(args, dev) -> int:
+    """Per-projection GPU times of the small workload (n = 512, k = 40, p = 10, q = 0, plain,
+    FP64) and of the medium one (n = 4096, k = 100, p = 10, q in {0, 1}, plain and scaled with
+    alpha by Alg. 5, FP32 and BF16x3), each a psdproj_run replayed from the graph cache, with the
+    oracle's time for the same projection on the host."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from oracle import rnla
+    from paper_2410_19208_amd.torch_api import Projector
+
+    rows = []
+    A, _, _ = workloads.make_matrix("small", 512, 1001, storage="fp64")
+    At = torch.from_numpy(A).to(dev)
+    pr = Projector(512, 40, 10, 0, "plain", "fp64", seed=0, device=dev)
+    t_gpu = timed(lambda: pr(At), 50, warm=3)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        rnla.project(A, 40, 10, 0, "plain", seed=0)
+    t_cpu = (time.perf_counter() - t0) / 5
+    rows.append({"config": "small n=512 k=40 p=10 q=0 plain fp64", "gpu_ms": round(1e3 * t_gpu, 4),
+                 "oracle_ms": round(1e3 * t_cpu, 2)})
+    A, _, _ = workloads.make_matrix("medium", 4096, 0, storage="fp32", noise=1e-3 / math.sqrt(4096))
+    At = torch.from_numpy(A).to(dev)
+    A64 = A.astype(np.float64)
+    for q in (0, 1):
+        for variant in ("plain", "scaled"):
+            t0 = time.perf_counter()
+            rnla.project(A64, 100, 10, q, variant, seed=0, omega_dtype=np.float32)
+            t_cpu = time.perf_counter() - t0
+            for prec in ("fp32", "bf16x3"):
+                pr = Projector(4096, 100, 10, q, variant, prec, seed=0, device=dev)
+                t_gpu = timed(lambda: pr(At), 20, warm=3)
+                rows.append({"config": f"medium n=4096 k=100 p=10 q={q} {variant} {prec}",
+                             "gpu_ms": round(1e3 * t_gpu, 4), "oracle_ms": round(1e3 * t_cpu, 1)})
+    for r in rows:
+        r["gpu_over_oracle_speedup"] = round(r["oracle_ms"] / r["gpu_ms"], 1)
+    out = {"metric": "per-projection time of the small and medium workloads (single requests)", "rows": rows,
+           "cores": int(host_cores()), "unit": "ms"}
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

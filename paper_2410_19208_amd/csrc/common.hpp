@@ -42,6 +42,11 @@ constexpr int RB_TILE = 128;                  // rebuild output tile (P)
 constexpr int APPLY_ROWS = 64;                // rows per apply/formw tile
 constexpr int GEMV_TILE = 256;                // GEMV tile edge (upper-triangle tiles of A)
 constexpr int MAX_SPLIT = 16;               // pass split-K factors 1 .. MAX_SPLIT
+// Tiles per workgroup of the streaming GEMV and rebuild kernels: a workgroup loops over its
+// problem's tiles with the stride of the problem's workgroup count (a multiple of 8 for the
+// rebuild, so every tile keeps its XCD), amortising launch, prologue and epilogue.
+constexpr int GV_PER_WG = 1;
+constexpr int RB_PER_WG = 1;
 constexpr int NSCAL = 16;
 constexpr int NISCAL = 16;
 
@@ -70,6 +75,7 @@ struct Prob {
   int32_t ktail, sketch;           // BF16X3 16-byte path: K rows ktail .. n-1 (n mod 32 of them)
                                    // are added by the pass reduction, not the pass (else n);
                                    // sketch: 0 Gaussian test matrix, 1 structured (+-1 Hadamard)
+  int32_t gv_tiles, rb_tiles;       // tiles of the GEMV (Alg. 4 product) and of the rebuild
   int32_t srht_m, csr;             // structured sketch: transform size 2^srht_m >= n; csr: A is
                                    // sparse (CSR, both triangles), A points to its values
   const int32_t* rowptr;           // CSR row starts (n + 1) and column indices

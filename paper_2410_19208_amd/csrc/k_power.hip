@@ -282,8 +282,12 @@ __global__ __launch_bounds__(GEMV_THREADS) void k_gemv(const Prob* __restrict__ 
     else spmv_rows<float>(p, t);
     return;
   }
-  if (p.prec == F64) gemv_tile<double, 4>(p, t);
-  else gemv_tile<float, 8>(p, t);
+  const int G = tstart[pi + 1] - tstart[pi];   // this problem's workgroups
+  for (int u = t; u < p.gv_tiles; u += G) {
+    if (p.prec == F64) gemv_tile<double, 4>(p, u);
+    else gemv_tile<float, 8>(p, u);
+    if (u + G < p.gv_tiles) lds_barrier();     // the next tile rewrites the column-sum stage
+  }
 }
 
 // alpha = |sigma1 - sigma2| (Alg. 5 line 4); E_ALPHA unless positive and finite.
@@ -319,9 +323,12 @@ __global__ void k_finalize(const Prob* __restrict__ probs, const int* __restrict
   *p.res = out;
 }
 
-int tiles_gemv(const Prob& p) {
+int gemv_tile_count(const Prob& p) {
   const int nb = (p.n + GEMV_TILE - 1) / GEMV_TILE;
   return p.csr ? nb : nb * (nb + 1) / 2;
+}
+int tiles_gemv(const Prob& p) {
+  return p.csr ? gemv_tile_count(p) : (gemv_tile_count(p) + GV_PER_WG - 1) / GV_PER_WG;
 }
 int tiles_gemv_rows(const Prob& p) { return (p.n + GEMV_TILE - 1) / GEMV_TILE; }
 int tiles_vec(const Prob& p) { return (p.ld + 1023) / 1024; }

@@ -267,20 +267,28 @@ __global__ __launch_bounds__(RB_THREADS) void k_rebuild(const Prob* __restrict__
   const int pi = find_prob(tstart, nprob, blockIdx.x);
   const Prob& p = probs[pi];
   const int t = blockIdx.x - tstart[pi];
+  const int G = tstart[pi + 1] - tstart[pi];   // this problem's workgroups, a multiple of 8
   const int nb = (p.n + RB_TILE - 1) / RB_TILE;
-  int I, J;
-  if (!tile_ij(t, nb, I, J)) return;
-  rebuild_tile<PREC>(p, I, J);
+  for (int u = t; u < p.rb_tiles; u += G) {
+    int I, J;
+    if (!tile_ij(u, nb, I, J)) continue;
+    rebuild_tile<PREC>(p, I, J);
+    if (u + G < p.rb_tiles) lds_barrier();     // the next tile rewrites the LDS stage
+  }
 }
 
 // A multiple of 8, so the next problem's tiles start on XCD 0: the lower tiles rounded up, or
 // for the XCD order 8 x the longest XCD tile list.
-int tiles_rebuild(const Prob& p) {
+int rebuild_tile_count(const Prob& p) {
   const int nb = (p.n + RB_TILE - 1) / RB_TILE;
   if (nb < RB_XCD_MIN) return (nb * (nb + 1) / 2 + 7) / 8 * 8;
   int mx = 0;
   for (int x = 0; x < 8; ++x) mx = std::max(mx, rb_xcd_tiles(x, nb));
   return 8 * mx;
+}
+int tiles_rebuild(const Prob& p) {
+  const int per_xcd = rebuild_tile_count(p) / 8;
+  return 8 * ((per_xcd + RB_PER_WG - 1) / RB_PER_WG);
 }
 
 // Dynamic LDS: the two-slice W_J ring, or later the half-tile stage (the larger of the two).

@@ -22,11 +22,13 @@ int tiles_reduce(const Prob& p);
 int tiles_gram(const Prob& p, bool full);
 int tiles_small(const Prob& p);       // one block per problem
 int tiles_apply(const Prob& p);
-int tiles_gemv(const Prob& p);
+int tiles_gemv(const Prob& p);       // workgroups (GV_PER_WG tiles each)
+int gemv_tile_count(const Prob& p);
 int tiles_gemv_rows(const Prob& p);  // one block per 256-row block row
 int tiles_bisect(const Prob& p);
 int tiles_invit(const Prob& p);
-int tiles_rebuild(const Prob& p);
+int tiles_rebuild(const Prob& p);    // workgroups (RB_PER_WG tiles each, a multiple of 8)
+int rebuild_tile_count(const Prob& p);
 
 void launch_omega(const Launch& L);
 void launch_power_init(const Launch& L, int which);

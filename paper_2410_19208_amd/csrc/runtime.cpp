@@ -186,6 +186,8 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   p.scal = (double*)at(pl.o_scal); p.iscal = (int32_t*)at(pl.o_iscal); p.drop = (int32_t*)at(pl.o_drop);
   p.res = res;
   p.npass_tiles = tiles_pass(p);
+  p.gv_tiles = gemv_tile_count(p);
+  p.rb_tiles = rebuild_tile_count(p);
   return p;
 }
 
