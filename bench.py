@@ -36,6 +36,17 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 # relative Frobenius distance to the FP64 oracle on the same inputs
 PARITY_TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5}
+# Alg. 5 with N <= PAIRED_MAX: both power iterations share each product (k_gemv2, N + 1 reads
+# of A's upper triangle); otherwise they run one after the other (k_gemv, 2 (N + 1) reads).
+PAIRED_MAX = 32
+
+
+def alg5_products(N):
+    """(kernel, products per scaled projection, algorithmic bytes per product beyond A's upper
+    triangle) of Alg. 5 with N iterations."""
+    if N <= PAIRED_MAX:
+        return "k_gemv2", N + 1, 4 * 8.0     # two FP64 vectors in, two out, per row
+    return "k_gemv", 2 * (N + 1), 2 * 8.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large_20k_bf16x3.md")
@@ -313,7 +324,8 @@ def main() -> int:
     flops_plain = passes * 2 * nn * r + 2 * nn * r1.r_plus
     flops_scaled = passes * 2 * nn * r + 2 * nn * r2.r_plus + 2 * (args.alpha_iters + 1) * 2 * nn
     bytes_plain = (passes + 1) * nn * es
-    bytes_scaled = bytes_plain + 2 * (args.alpha_iters + 1) * nn * es
+    gk, gprod, gvec = alg5_products(args.alpha_iters)
+    bytes_scaled = bytes_plain + gprod * (n * (n + 1) / 2 * es + gvec * n)
     step_s = ms_per_step / 1e3
     tflops = (flops_plain + flops_scaled) / step_s / 1e12
     gbs = (bytes_plain + bytes_scaled) / step_s / 1e9
@@ -325,10 +337,11 @@ def main() -> int:
     d = dom_timed
     bound, unit, peak = "hbm", "GB/s", HBM_PEAK_GBS
     launches_per_step = d["launches"] / args.steps
-    if dom == "k_gemv":
-        per_unit = n * (n + 1) / 2 * es + 2 * n * 8.0
-        units = 2 * (args.alpha_iters + 1)
-        note = "upper triangle of the symmetric A read once per product plus two FP64 vectors"
+    if dom == gk:
+        per_unit = n * (n + 1) / 2 * es + gvec * n
+        units = gprod
+        note = ("upper triangle of the symmetric A read once per product plus the FP64 vectors"
+                + (" (both power iterations of Alg. 5 per product)" if gk == "k_gemv2" else ""))
     elif dom == "k_pass":
         # Algorithmic bytes: one read of A per problem-pass, n^2 s (the problems of a grouped
         # launch that stream the same A share its reads in L2, so the launch moves fewer bytes
@@ -375,7 +388,7 @@ def main() -> int:
     streaming = {}
     for kname, per_problem, problems_step in (
             ("k_pass", nn * es, 2 * passes),
-            ("k_gemv", n * (n + 1) / 2 * es + 2 * n * 8.0, 2 * (args.alpha_iters + 1)),
+            (gk, n * (n + 1) / 2 * es + gvec * n, gprod),
             ("k_rebuild", nn * es, 2)):
         if kname in kern:
             kd = kern[kname]
@@ -832,6 +845,7 @@ def run_sdls(args, dev) -> int:
     es = 4
     models = {"k_pass": (n * n * es * 2 * (q + 1) / per_iter.get("k_pass", 1), "one read of A per pass"),
               "k_gemv": (n * (n + 1) / 2 * es + 2 * n * 8, "upper triangle of X per product"),
+              "k_gemv2": (n * (n + 1) / 2 * es + 4 * n * 8, "upper triangle of X per product of both runs"),
               "k_rebuild": (n * n * es, "P written once"),
               "k_sdls_form": ((m + 2) * n * n * es, "C and the A_i read, X written"),
               "k_sdls_trace": ((m + 1) * n * n * es, "the A_i and P read")}
@@ -894,7 +908,7 @@ def _step_pair_mode(args, dev, name, make_pair, bytes_model, note):
         rf = roofline_entry(dom, kern[dom]["avg_us"], work, "hbm", HBM_PEAK_GBS, "GB/s", model)
     # the streaming kernels against the HBM roofline as well
     stream = {}
-    for kk in ("k_pass", "k_gemv", "k_rebuild"):
+    for kk in ("k_pass", "k_gemv", "k_gemv2", "k_rebuild"):
         if kk in kern:
             w, m = bytes_model(kk, kern)
             stream[kk] = roofline_entry(kk, kern[kk]["avg_us"], w, "hbm", HBM_PEAK_GBS, "GB/s", m)
@@ -961,10 +975,12 @@ def run_sparse(args, dev) -> int:
         per_problem = {"k_rebuild": (float(n) * n * es, "P written once"),
                        "k_pass": (nnz * (4 + es) + (n + 1) * 4 + n * (k + p) * es,
                                   "the CSR arrays and the panel read once per pass"),
-                       "k_gemv": (nnz * (4 + es) + (n + 1) * 4 + 2 * n * 8, "the CSR arrays and two vectors")}
+                       "k_gemv": (nnz * (4 + es) + (n + 1) * 4 + 2 * n * 8, "the CSR arrays and two vectors"),
+                       "k_gemv2": (nnz * (4 + es) + (n + 1) * 4 + 4 * n * 8, "the CSR arrays and four vectors")}
         w, m = per_problem.get(dom, (float("nan"), "no byte model"))
         lpc = kern[dom]["launches_per_call"]
-        problems = {"k_rebuild": 2, "k_pass": 2 * (2 * q + 2), "k_gemv": 2 * (args.alpha_iters + 1)}.get(dom, lpc)
+        gk, gprod, _ = alg5_products(args.alpha_iters)
+        problems = {"k_rebuild": 2, "k_pass": 2 * (2 * q + 2), gk: gprod}.get(dom, lpc)
         return w * problems / lpc, m
     return _step_pair_mode(args, dev, f"sparse_20k: n={n}, {nnz / n:.1f} stored entries per row (CSR, both "
                                       f"triangles), k={k}, p={p}, q={q}; one plain + one scaled projection per step",
@@ -1009,8 +1025,9 @@ def run_sketch(args, dev) -> int:
     def bytes_model(dom, kern):
         lpc = kern[dom]["launches_per_call"]
         per = {"k_pass": (float(n) * n * es, 2 * (2 * q + 2), "one read of A per pass and problem"),
-               "k_gemv": (n * (n + 1) / 2 * es + 2 * n * 8, 2 * (args.alpha_iters + 1), "upper triangle per product"),
                "k_rebuild": (float(n) * n * es, 2, "P written once")}
+        gk, gprod, gvec = alg5_products(args.alpha_iters)
+        per[gk] = (n * (n + 1) / 2 * es + gvec * n, gprod, "upper triangle per product")
         if dom not in per:
             return float("nan"), "no byte model"
         w, problems, m = per[dom]

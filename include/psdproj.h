@@ -11,7 +11,14 @@
  *                    Q^T B Q = V D V^T
  *                    P = alpha Q V (max(D, 1) - I) V^T Q^T
  *                    alpha is given, or estimated by Alg. 5 (two runs of the power
- *                    iteration of Alg. 4, N steps each).
+ *                    iteration of Alg. 4, N steps each).  For N <= 32 both runs share
+ *                    each read of X: the first run as written, and beside it a Krylov
+ *                    basis of the second run's start vector whose shifts follow the first
+ *                    run's sigma_1 estimate (tr(X)/n for the first two), from which the
+ *                    second run's last two iterates are formed once sigma_1 is known
+ *                    (N + 1 products of two vectors instead of 2 (N + 1) of one; alpha
+ *                    equal to the literal iteration's to near FP64 rounding).  For N > 32
+ *                    the runs are made one after the other.
  *
  * The oversampling parameter l of the paper is called p here; the sketch width is r = k + p.
  * The range finder orthonormalises after every product with X (subspace iteration), which
@@ -147,7 +154,7 @@ typedef struct {
     size_t   evals;      /* eigenvalues of C, ascending, r doubles */
     size_t   weights;    /* clamped weights of the kept eigenpairs (descending eigenvalue order), r_plus doubles */
     size_t   factor;     /* W = Q V_keep diag(sqrt(w)), n x r_plus, panel precision; P = W W^T */
-    size_t   power_vec;  /* last power-iteration vector, n doubles */
+    size_t   power_vec;  /* the two FP64 vectors (ping-pong) of the power iteration of Alg. 4 */
     size_t   y_panel;    /* output of the last pass over A, M(Q), n x r, panel precision */
     size_t   gram;       /* last CholeskyQR Gram matrix, r x r double, ld r_pad, column-major */
     size_t   total;      /* workspace bytes */

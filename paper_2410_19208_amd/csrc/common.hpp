@@ -49,10 +49,14 @@ constexpr int GV_PER_WG = 1;
 constexpr int RB_PER_WG = 1;
 constexpr int NSCAL = 16;
 constexpr int NISCAL = 16;
+// Alg. 5 with N <= PAIRED_MAX runs its two power iterations over one stream of two-vector
+// products (the second run's iterates are rebuilt from a shifted Krylov basis); larger N
+// runs them one after the other.
+constexpr int PAIRED_MAX = 32;
 
 // scal[] slots
 enum { S_ALPHA = 0, S_SIGMA1 = 1, S_SIGMA2 = 2, S_NRM = 3, S_INV = 4, S_SHIFT = 5, S_TNORM = 6,
-       S_THRESH = 7 };
+       S_THRESH = 7, S_INVB = 8, S_MU = 9, S_MU0 = 10 };
 // iscal[] slots
 enum { I_STATUS = 0, I_RPLUS = 1, I_NU = 2, I_COUNTER = 3, I_NEWTON = 4, I_NDROP = 5, I_PP = 6, I_WELL = 7 };
 
@@ -78,6 +82,7 @@ struct Prob {
   int32_t gv_tiles, rb_tiles;       // tiles of the GEMV (Alg. 4 product) and of the rebuild
   int32_t srht_m, csr;             // structured sketch: transform size 2^srht_m >= n; csr: A is
                                    // sparse (CSR, both triangles), A points to its values
+  int32_t paired, pad0;            // Alg. 5's two runs share one stream of products (N <= PAIRED_MAX)
   const int32_t* rowptr;           // CSR row starts (n + 1) and column indices
   const int32_t* colidx;
   void* zr;                        // CSR passes: the pass operand row-major (n x rpad)
@@ -95,8 +100,10 @@ struct Prob {
   double* G; double* F; double* C; double* H; double* V;  // rpad x rpad, column-major
   double* evals; double* tau; double* td; double* te; double* wts; double* xt;  // eig scratch
   double* vec;                     // power vectors: 2 x ld
-  double* vpart;                   // GEMV: sum of squares per block row
-  double* gvp;                     // GEMV tile partials: nb x nb x GEMV_TILE
+  double* vpart;                   // GEMV: sum of squares per block row (2 x nb when paired)
+  double* gvp;                     // GEMV tile partials: nb x nb x GEMV_TILE (twice when paired)
+  double* bh;                      // paired Alg. 5: Krylov basis b_0 .. b_{N+1}, (N + 2) x ld
+  double* pw;                      // paired Alg. 5: rho_0 .. rho_{N+1}, then mu_0 .. mu_{N+1}
   double* scal;                    // NSCAL doubles
   int32_t* iscal;                  // NISCAL ints
   int32_t* drop;                   // rpad flags

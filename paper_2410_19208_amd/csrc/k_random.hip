@@ -132,6 +132,77 @@ __global__ __launch_bounds__(256) void k_power_init(const Prob* __restrict__ pro
   }
 }
 
+// Diagonal entry X_ii (dense in the storage type; CSR: the stored entries of row i in column i,
+// added in storage order, indices outside the arrays skipped).
+__device__ __forceinline__ double diag_entry(const Prob& p, int i) {
+  if (p.csr) {
+    const int64_t k0 = max((int64_t)p.rowptr[i], (int64_t)0), k1 = min((int64_t)p.rowptr[i + 1], p.lda);
+    double d = 0.0;
+    for (int64_t k = k0; k < k1; ++k)
+      if (p.colidx[k] == i) d += (p.prec == F64) ? ((const double*)p.A)[k] : (double)((const float*)p.A)[k];
+    return d;
+  }
+  const int64_t o = (int64_t)i * p.lda + i;
+  return (p.prec == F64) ? ((const double*)p.A)[o] : (double)((const float*)p.A)[o];
+}
+
+// Start of Alg. 5 in its paired form: the first run's start vector (stream 1) into the vector
+// the next product reads, the second run's (stream 2) into basis slot 0, and the shift of the
+// basis' first two products, mu_0 = tr(X)/n: each block adds its rows' diagonal entries in a
+// fixed order and the last block to finish (integer ticket) adds the block sums in block order.
+__global__ __launch_bounds__(256) void k_power_init2(const Prob* __restrict__ probs, const int* __restrict__ tstart,
+                                                     int nprob) {
+  const int pi = find_prob(tstart, nprob, blockIdx.x);
+  const Prob& p = probs[pi];
+  const int blk = blockIdx.x - tstart[pi];
+  const int G = tstart[pi + 1] - tstart[pi];
+  const int base = blk * 1024;
+  double* v = p.vec + (int64_t)(p.iscal[I_PP] & 1) * p.ld;
+  __shared__ double red[256 / 64];
+  __shared__ double rows[256];
+  __shared__ int is_last;
+  const int x = threadIdx.x;
+  double ds = 0.0;
+  for (int e = x; e < 1024; e += 256) {
+    const int i = base + e;
+    if (i >= p.ld) break;
+    const bool in = i < p.n;
+    v[i] = in ? gauss_at(p.seed, 1u, (uint64_t)i) : 0.0;
+    p.bh[i] = in ? gauss_at(p.seed, 2u, (uint64_t)i) : 0.0;
+    if (in) ds += diag_entry(p, i);
+  }
+  const double ws = wave_sum(ds);
+  if ((x & 63) == 0) red[x >> 6] = ws;
+  __syncthreads();
+  if (x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < 256 / 64; ++w) tot += red[w];
+    p.vpart[blk] = tot;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    is_last = (atomicAdd(&p.iscal[I_COUNTER], 1) == G - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double tr = 0.0;
+  for (int r0 = 0; r0 < G; r0 += 256) {
+    if (r0 + x < G) rows[x] = p.vpart[r0 + x];
+    __syncthreads();
+    if (x == 0)
+      for (int r = 0; r < 256 && r0 + r < G; ++r) tr += rows[r];
+    __syncthreads();
+  }
+  if (x == 0) {
+    const double mu0 = tr / (double)p.n;
+    p.scal[S_INV] = 1.0;
+    p.scal[S_INVB] = 1.0;
+    p.scal[S_MU0] = mu0;
+    p.scal[S_MU] = mu0;
+    p.pw[0] = 1.0;
+    p.iscal[I_COUNTER] = 0;
+  }
+}
+
 __global__ void k_words(uint64_t seed, uint32_t stream, uint64_t c0, int64_t count, uint32_t* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -162,6 +233,9 @@ void launch_omega(const Launch& L) {
 }
 void launch_power_init(const Launch& L, int which) {
   hipLaunchKernelGGL(k_power_init, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob, which);
+}
+void launch_power_init2(const Launch& L) {
+  hipLaunchKernelGGL(k_power_init2, dim3(L.grid), dim3(256), 0, L.stream, L.probs, L.tstart, L.nprob);
 }
 void launch_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count, uint32_t* out, hipStream_t s) {
   if (count <= 0) return;

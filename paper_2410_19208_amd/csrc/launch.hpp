@@ -32,6 +32,7 @@ int rebuild_tile_count(const Prob& p);
 
 void launch_omega(const Launch& L);
 void launch_power_init(const Launch& L, int which);
+void launch_power_init2(const Launch& L);
 void launch_words(uint64_t seed, uint32_t stream_id, uint64_t c0, int64_t count, uint32_t* out, hipStream_t s);
 void launch_gauss(uint64_t seed, uint32_t stream_id, uint64_t start, int64_t count, double* out, hipStream_t s);
 void launch_srht(uint64_t seed, int n, int r, double* out, hipStream_t s);
@@ -71,5 +72,8 @@ void launch_finalize(const Launch& L);
 void launch_gemv(const Launch& L, int last);
 void launch_gemv_finish(const Launch& L, int last);
 void launch_alpha(const Launch& L);
+void launch_gemv2(const Launch& L, int j);
+void launch_gemv2_finish(const Launch& L, int j);
+void launch_alpha2(const Launch& L);
 
 }  // namespace psd

@@ -78,6 +78,7 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.es = (pl.prec == F64) ? 8 : 4;
   pl.ncb = pl.rpad / 16;
   pl.alpha_mode = alpha_mode;
+  pl.paired = (alpha_mode == 1 && d->alpha_iters <= PAIRED_MAX) ? 1 : 0;
   pl.csr = (d->flags & PSDPROJ_FLAG_CSR) ? 1 : 0;
   // split-K, at most 8 (one K chunk per XCD).  FP64: enough workgroups to fill 256 CUs twice.
   // FP32 / BF16X3 (one 8-wave workgroup per CU): 8 chunks of at least 64 columns, so each
@@ -125,8 +126,11 @@ psdproj_status make_plan(const psdproj_desc* d, Plan& pl) {
   pl.o_wts = take(PSDPROJ_MAX_RANK * 8);
   pl.o_vec = take((size_t)2 * pl.ld * 8);
   const size_t gnb = (size_t)(n + GEMV_TILE - 1) / GEMV_TILE;
-  pl.o_vpart = take(gnb * 8);
-  pl.o_gvp = take(gnb * gnb * GEMV_TILE * 8);
+  const size_t nvec = pl.paired ? 2 : 1;   // vectors per product
+  pl.o_vpart = take(nvec * gnb * 8);
+  pl.o_gvp = take(nvec * gnb * gnb * GEMV_TILE * 8);
+  pl.o_bh = pl.paired ? take((size_t)(d->alpha_iters + 2) * pl.ld * 8) : 0;
+  pl.o_pw = pl.paired ? take((size_t)2 * (PAIRED_MAX + 2) * 8) : 0;
   pl.o_scal = take(NSCAL * 8);
   pl.o_iscal = take(NISCAL * 4);
   pl.o_drop = take(PSDPROJ_MAX_RANK * 4);
@@ -183,6 +187,9 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   p.td = (double*)at(pl.o_td); p.te = (double*)at(pl.o_te); p.wts = (double*)at(pl.o_wts);
   p.vec = (double*)at(pl.o_vec); p.vpart = (double*)at(pl.o_vpart);
   p.gvp = (double*)at(pl.o_gvp);
+  p.paired = pl.paired;
+  p.bh = (double*)(pl.paired ? at(pl.o_bh) : nullptr);
+  p.pw = (double*)(pl.paired ? at(pl.o_pw) : nullptr);
   p.scal = (double*)at(pl.o_scal); p.iscal = (int32_t*)at(pl.o_iscal); p.drop = (int32_t*)at(pl.o_drop);
   p.res = res;
   p.npass_tiles = tiles_pass(p);
@@ -198,8 +205,10 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
 static bool active_in(const Plan& pl, const Stage& st) {
   switch (st.when) {
     case W_ALL: return true;
-    case W_ALPHA: return pl.alpha_mode == 1;
-    case W_ALPHA_ITER: return pl.alpha_mode == 1 && st.iter < pl.d.alpha_iters;
+    case W_SEQ: return pl.alpha_mode == 1 && !pl.paired;
+    case W_SEQ_ITER: return pl.alpha_mode == 1 && !pl.paired && st.iter < pl.d.alpha_iters;
+    case W_PAIRED: return pl.paired;
+    case W_PAIRED_ITER: return pl.paired && st.iter <= pl.d.alpha_iters;
     case W_POWER: return st.iter < pl.d.q;
   }
   return false;
@@ -209,9 +218,9 @@ static int stage_tiles(const Prob& p, int kind) {
   switch (kind) {
     case K_SETUP: case K_ALPHA: case K_CHOL: case K_TRIDIAG: case K_FINAL: return 1;
     case K_OMEGA: return tiles_omega(p);
-    case K_PINIT: return tiles_vec(p);
-    case K_GEMV: return tiles_gemv(p);
-    case K_GEMV_FIN: return tiles_gemv_rows(p);
+    case K_PINIT: case K_PINIT2: case K_ALPHA2: return tiles_vec(p);
+    case K_GEMV: case K_GEMV2: return tiles_gemv(p);
+    case K_GEMV_FIN: case K_GEMV2_FIN: return tiles_gemv_rows(p);
     case K_PASS: return p.csr ? tiles_pass(p) : rup(tiles_pass(p), 8);
     case K_ZT: return p.csr ? tiles_zt(p) : 0;
     case K_PRED: return tiles_reduce(p);
@@ -226,21 +235,32 @@ static int stage_tiles(const Prob& p, int kind) {
   return 0;
 }
 
-static void stage_list(int max_iters, int max_q, std::vector<Stage>& out) {
+// max_seq / max_paired: the largest N of Alg. 5 among the problems that run its two power
+// iterations one after the other / over shared products (0: none).
+static void stage_list(int max_seq, int max_paired, int max_q, std::vector<Stage>& out) {
   auto add = [&](int kind, int arg, int when, int iter) { out.push_back(Stage{kind, arg, when, iter}); };
   add(K_SETUP, 0, W_ALL, 0);
   add(K_OMEGA, 0, W_ALL, 0);
-  if (max_iters > 0) {
-    for (int run = 0; run < 2; ++run) {
-      add(K_PINIT, run, W_ALPHA, 0);
-      for (int it = 0; it < max_iters; ++it) {
-        add(K_GEMV, 0, W_ALPHA_ITER, it);
-        add(K_GEMV_FIN, 0, W_ALPHA_ITER, it);
-      }
-      add(K_GEMV, run + 1, W_ALPHA, 0);
-      add(K_GEMV_FIN, run + 1, W_ALPHA, 0);
+  if (max_paired > 0) {
+    // products j = 0 .. N with [v_j, b_j], then the second run's iterates from the basis
+    add(K_PINIT2, 0, W_PAIRED, 0);
+    for (int j = 0; j <= max_paired; ++j) {
+      add(K_GEMV2, j, W_PAIRED_ITER, j);
+      add(K_GEMV2_FIN, j, W_PAIRED_ITER, j);
     }
-    add(K_ALPHA, 0, W_ALPHA, 0);
+    add(K_ALPHA2, 0, W_PAIRED, 0);
+  }
+  if (max_seq > 0) {
+    for (int run = 0; run < 2; ++run) {
+      add(K_PINIT, run, W_SEQ, 0);
+      for (int it = 0; it < max_seq; ++it) {
+        add(K_GEMV, 0, W_SEQ_ITER, it);
+        add(K_GEMV_FIN, 0, W_SEQ_ITER, it);
+      }
+      add(K_GEMV, run + 1, W_SEQ, 0);
+      add(K_GEMV_FIN, run + 1, W_SEQ, 0);
+    }
+    add(K_ALPHA, 0, W_SEQ, 0);
   }
   // o: position of the orthonormalisation in each problem's sequence (see orth_single)
   auto orth = [&](int when, int iter, int o) {
@@ -294,13 +314,14 @@ void build_schedule(const Plan* const* plans, int count, Schedule& s) {
     s.groups.push_back({i, j - i, gkey(s.order[i]), plans[s.order[i]]->ncb});
     i = j;
   }
-  int max_iters = 0, max_q = 0;
+  int max_seq = 0, max_paired = 0, max_q = 0;
   for (int i = 0; i < count; ++i) {
-    if (plans[i]->alpha_mode == 1) max_iters = std::max(max_iters, plans[i]->d.alpha_iters);
+    if (plans[i]->paired) max_paired = std::max(max_paired, plans[i]->d.alpha_iters);
+    else if (plans[i]->alpha_mode == 1) max_seq = std::max(max_seq, plans[i]->d.alpha_iters);
     max_q = std::max(max_q, plans[i]->d.q);
   }
   std::vector<Stage> stages;
-  stage_list(max_iters, max_q, stages);
+  stage_list(max_seq, max_paired, max_q, stages);
   // tile counts need only the sizes, so a Prob without pointers is enough here
   std::vector<Prob> shape(count);
   for (int i = 0; i < count; ++i) shape[i] = make_prob(*plans[s.order[i]], nullptr, nullptr, 0, nullptr, 0, nullptr);
@@ -472,6 +493,10 @@ psdproj_status enqueue(const Schedule& s, unsigned char* hdr, hipStream_t stream
       case K_GEMV: launch_gemv(L, R.arg); break;
       case K_GEMV_FIN: launch_gemv_finish(L, R.arg); break;
       case K_ALPHA: launch_alpha(L); break;
+      case K_PINIT2: launch_power_init2(L); break;
+      case K_GEMV2: launch_gemv2(L, R.arg); break;
+      case K_GEMV2_FIN: launch_gemv2_finish(L, R.arg); break;
+      case K_ALPHA2: launch_alpha2(L); break;
       case K_PASS: (R.prec >= 8) ? launch_spmm(L) : launch_pass(L, R.prec, R.ncb); break;
       case K_ZT: launch_zt(L); break;
       case K_PRED: launch_pass_reduce(L); break;
@@ -501,7 +526,7 @@ static const char* const KIND_NAMES[K_NKINDS] = {
     "k_setup", "k_omega", "k_power_init", "k_gemv", "k_alpha", "k_pass", "k_pass_reduce", "k_gram",
     "k_gram_full", "k_gram_reduce", "k_chol", "k_apply", "k_tridiag", "k_bisect", "k_invit", "k_rebuild",
     "k_finalize", "k_gemv_finish", "k_apply_factor", "k_backxf", "k_zt", "k_sdls_form", "k_sdls_trace",
-    "k_sdls_update", "k_gemm64", "k_exact_misc"};
+    "k_sdls_update", "k_gemm64", "k_exact_misc", "k_power_init2", "k_gemv2", "k_gemv2_finish", "k_alpha2"};
 
 // ------------------------------------------------------------------------------ HIP graphs
 // A schedule's launches reach the problems only through the header at `hdr` (each kernel

@@ -11,9 +11,13 @@ namespace psd {
 enum Kind {
   K_SETUP, K_OMEGA, K_PINIT, K_GEMV, K_ALPHA, K_PASS, K_PRED, K_GRAM_SYM, K_GRAM_FULL, K_GRED,
   K_CHOL, K_APPLY, K_TRIDIAG, K_BISECT, K_INVIT, K_REBUILD, K_FINAL, K_GEMV_FIN, K_FACTOR, K_BACKXF, K_ZT,
-  K_SDLS_FORM, K_SDLS_TRACE, K_SDLS_UPDATE, K_GEMM64, K_EXACT_MISC, K_NKINDS
+  K_SDLS_FORM, K_SDLS_TRACE, K_SDLS_UPDATE, K_GEMM64, K_EXACT_MISC, K_PINIT2, K_GEMV2, K_GEMV2_FIN,
+  K_ALPHA2, K_NKINDS
 };
-enum When { W_ALL, W_ALPHA, W_ALPHA_ITER, W_POWER };
+// Which problems take part in a stage: all; those estimating alpha with the two runs one after
+// the other (N > PAIRED_MAX) or sharing products (N <= PAIRED_MAX), at every iteration or only
+// below their N (sequential) or N + 1 (paired); those with q > iter.
+enum When { W_ALL, W_SEQ, W_SEQ_ITER, W_PAIRED, W_PAIRED_ITER, W_POWER };
 
 struct Stage { int kind, arg, when, iter; };
 
@@ -35,13 +39,13 @@ struct Schedule {
 // An immutable, validated problem description with its tiling and workspace layout.
 struct Plan {
   psdproj_desc d;
-  int r, rpad, ld, prec, es, ncb, alpha_mode, csr;
+  int r, rpad, ld, prec, es, ncb, alpha_mode, csr, paired;
   int split, kchunk, ngchunk, rwpad;
   size_t region;          // workspace bytes of the problem's own buffers
   size_t header_single;   // header bytes of a single run
   size_t o_zm, o_zhi, o_zlo, o_y, o_part, o_q1, o_wf, o_whi, o_wlo, o_gpart;
   size_t o_G, o_F, o_C, o_H, o_V, o_xt, o_evals, o_tau, o_td, o_te, o_wts;
-  size_t o_vec, o_vpart, o_gvp, o_scal, o_iscal, o_drop, o_zr;
+  size_t o_vec, o_vpart, o_gvp, o_scal, o_iscal, o_drop, o_zr, o_bh, o_pw;
   Schedule single;        // launch schedule of a single run (header_single bytes of header)
 };
 
