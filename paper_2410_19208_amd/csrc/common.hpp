@@ -56,7 +56,7 @@ constexpr int PAIRED_MAX = 32;
 
 // scal[] slots
 enum { S_ALPHA = 0, S_SIGMA1 = 1, S_SIGMA2 = 2, S_NRM = 3, S_INV = 4, S_SHIFT = 5, S_TNORM = 6,
-       S_THRESH = 7, S_INVB = 8, S_MU = 9, S_MU0 = 10 };
+       S_THRESH = 7, S_GL = 8, S_GU = 9, S_PIVMIN = 10, S_INVB = 11, S_MU = 12, S_MU0 = 13 };
 // iscal[] slots
 enum { I_STATUS = 0, I_RPLUS = 1, I_NU = 2, I_COUNTER = 3, I_NEWTON = 4, I_NDROP = 5, I_PP = 6, I_WELL = 7 };
 

@@ -55,8 +55,8 @@ __global__ __launch_bounds__(256) void k_bisect(const Prob* __restrict__ probs, 
   if (j >= r) return;
   const gmem<const double>* d = gp((const double*)p.td);
   const gmem<const double>* e2 = gp((const double*)p.evals + PSDPROJ_MAX_RANK);
-  const double pivmin = p.scal[10];
-  double lo = p.scal[8], hi = p.scal[9];
+  const double pivmin = p.scal[S_PIVMIN];
+  double lo = p.scal[S_GL], hi = p.scal[S_GU];
   if (!(isfinite(lo) && isfinite(hi))) {
     if (lane == 0) p.evals[j] = __builtin_nan("");
     return;

@@ -1,82 +1,125 @@
 // Kernels of the exact projection X_+ = U max(D, 0) U^T (Thm 1) computed through the matrix sign
 // function, X_+ = (X + X sign(X)) / 2 (the polar form (X + |X|)/2 with |X| = X sign(X)):
-//   k_gemm64:      C = alpha A B + beta D, n x n, FP64 on v_mfma_f64_16x16x4f64 (64 x 64 tiles,
-//                  4 waves of 32 x 32, K steps of 16 through LDS);
+//   k_gemm64:      C = alpha A B + beta D, n x n, FP64 on v_mfma_f64_16x16x4f64 (128 x 128 tiles,
+//                  4 waves of 64 x 64, K stages of 16 through two LDS buffers);
 //   k_ex_sumsq / k_ex_finish: ||X||_F in FP64, fixed order;
 //   k_ex_scale:    S = X / ||X||_F (FP64 copy), and X itself in FP64;
 //   k_ex_poly:     W = 3 I - a^2 W, in place;
 //   k_ex_final:    P = (Q + Q^T) / 2 in the storage precision (Q = (X + X S) / 2), exactly
 //                  symmetric; k_ex_trace: Tr(S) for the count of positive eigenvalues.
+#include <atomic>
+
 #include "common.hpp"
 #include "exact_kernels.hpp"
 
 namespace psd {
 
 constexpr int GM_T = 256;      // threads per GEMM workgroup (4 waves)
-constexpr int GM_B = 64;       // output tile edge
+constexpr int GM_B = 128;      // output tile edge; each wave computes 64 x 64
 constexpr int GM_K = 16;       // K per LDS stage
 constexpr int GM_PAD = 2;      // doubles of padding per LDS row
+constexpr int GM_LD = GM_B + GM_PAD;
 
 // A, B, C, D column-major with leading dimensions; element (i, j) of A at A[j * lda + i].
-__global__ __launch_bounds__(GM_T) void k_gemm64(int n, const double* __restrict__ A, int64_t lda,
-                                                 const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
-                                                 int64_t ldc, double alpha, const double* __restrict__ D,
-                                                 int64_t ldd, double beta) {
-  __shared__ double sA[GM_K][GM_B + GM_PAD];   // sA[k][i] = A(i0 + i, k0 + k)
-  __shared__ double sB[GM_K][GM_B + GM_PAD];   // sB[k][j] = B(k0 + k, j0 + j)
+// Tile 128 x 128 per workgroup, 4 waves of 64 x 64 (4 x 4 blocks of v_mfma_f64_16x16x4f64).  The
+// A and B slices of a K stage (16 columns of A's 128 rows, 16 rows of B's 128 columns) go
+// through two LDS buffers: the next stage's global loads are issued into registers before the
+// current stage's products and stored to the other buffer after them, one barrier per stage.
+// Interior stages with even leading dimensions load 16 bytes per thread and access; other stages
+// load element by element with zeros outside n x n.
+__global__ __launch_bounds__(GM_T, 2) void k_gemm64(int n, const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                                                    int64_t ldc, double alpha, const double* __restrict__ D,
+                                                    int64_t ldd, double beta) {
+  extern __shared__ __attribute__((aligned(16))) double gsm[];
+  double* sA = gsm;                       // [2][GM_K][GM_LD]: sA[b][k][i] = A(i0 + i, k0 + k)
+  double* sB = gsm + 2 * GM_K * GM_LD;    // [2][GM_K][GM_LD]: sB[b][k][j] = B(k0 + k, j0 + j)
   const int i0 = blockIdx.x * GM_B, j0 = blockIdx.y * GM_B;
   const int tid = threadIdx.x, wave = wave_id(), lane = tid & 63;
   const int wr = wave & 1, wc = wave >> 1, li = lane & 15, kg = lane >> 4;
   const gmem<const double>* Ag = gp(A);
   const gmem<const double>* Bg = gp(B);
-  f64x4 acc[2][2];
+  const bool vec = ((lda | ldb) & 1) == 0;
+  f64x4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < n; k0 += GM_K) {
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+
+  // thread's share of a stage: 4 pairs of A (rows 2 ia, 2 ia + 1 of column ka) and 4 pairs of B
+  // (rows 2 kb, 2 kb + 1 of column jb)
+  f64x2 ra[4], rb[4];
+  auto load = [&](int k0) {
+    const bool inner = vec && i0 + GM_B <= n && j0 + GM_B <= n && k0 + GM_K <= n;
 #pragma unroll
-    for (int u = 0; u < GM_B * GM_K / GM_T; ++u) {
+    for (int u = 0; u < 4; ++u) {
       const int e = tid + GM_T * u;
-      {  // A: 64 consecutive rows of one column per 64 threads
-        const int k = e / GM_B, i = e % GM_B;
-        const int gi = i0 + i, gk = k0 + k;
-        sA[k][i] = (gi < n && gk < n) ? Ag[(int64_t)gk * lda + gi] : 0.0;
-      }
-      {  // B: 16 consecutive rows of one column per 16 threads
-        const int j = e / GM_K, k = e % GM_K;
-        const int gj = j0 + j, gk = k0 + k;
-        sB[k][j] = (gj < n && gk < n) ? Bg[(int64_t)gj * ldb + gk] : 0.0;
+      const int ka = e >> 6, ia = e & 63;          // A: 64 pairs of rows per column
+      const int jb = e >> 3, kb = e & 7;           // B: 8 pairs of rows per column
+      const int gi = i0 + 2 * ia, gka = k0 + ka;
+      const int gj = j0 + jb, gkb = k0 + 2 * kb;
+      if (inner) {
+        ra[u] = *(const gmem<f64x2>*)(Ag + (int64_t)gka * lda + gi);
+        rb[u] = *(const gmem<f64x2>*)(Bg + (int64_t)gj * ldb + gkb);
+      } else {
+        ra[u][0] = (gi < n && gka < n) ? Ag[(int64_t)gka * lda + gi] : 0.0;
+        ra[u][1] = (gi + 1 < n && gka < n) ? Ag[(int64_t)gka * lda + gi + 1] : 0.0;
+        rb[u][0] = (gj < n && gkb < n) ? Bg[(int64_t)gj * ldb + gkb] : 0.0;
+        rb[u][1] = (gj < n && gkb + 1 < n) ? Bg[(int64_t)gj * ldb + gkb + 1] : 0.0;
       }
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+    double* a = sA + buf * GM_K * GM_LD;
+    double* b = sB + buf * GM_K * GM_LD;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + GM_T * u;
+      const int ka = e >> 6, ia = e & 63;
+      const int jb = e >> 3, kb = e & 7;
+      *(f64x2*)(a + ka * GM_LD + 2 * ia) = ra[u];
+      b[(2 * kb) * GM_LD + jb] = rb[u][0];
+      b[(2 * kb + 1) * GM_LD + jb] = rb[u][1];
+    }
+  };
+
+  const int nst = (n + GM_K - 1) / GM_K;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load((st + 1) * GM_K);
+    const double* a = sA + cur * GM_K * GM_LD;
+    const double* b = sB + cur * GM_K * GM_LD;
 #pragma unroll
     for (int kk = 0; kk < GM_K; kk += 4) {
-      double a[2], b[2];
+      double av[4], bv[4];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        a[t] = sA[kk + kg][32 * wr + 16 * t + li];
-        b[t] = sB[kk + kg][32 * wc + 16 * t + li];
+      for (int t = 0; t < 4; ++t) {
+        av[t] = a[(kk + kg) * GM_LD + 64 * wr + 16 * t + li];
+        bv[t] = b[(kk + kg) * GM_LD + 64 * wc + 16 * t + li];
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
     }
+    if (st + 1 < nst) store(cur ^ 1);   // the other buffer: its last readers passed the previous barrier
     __syncthreads();
   }
   // lane (li, kg) of acc[x][y] holds rows acc_row<true>(kg, v) of block (x, y), column li
   gmem<double>* Cg = gp(C);
   const gmem<const double>* Dg = gp(D);
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      const int gj = j0 + 32 * wc + 16 * y + li;
+    for (int y = 0; y < 4; ++y) {
+      const int gj = j0 + 64 * wc + 16 * y + li;
       if (gj >= n) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int gi = i0 + 32 * wr + 16 * x + acc_row<true>(kg, v);
+        const int gi = i0 + 64 * wr + 16 * x + acc_row<true>(kg, v);
         if (gi >= n) continue;
         double r = alpha * acc[x][y][v];
         if (beta != 0.0) r = fma(beta, Dg[(int64_t)gj * ldd + gi], r);
@@ -176,10 +219,24 @@ int exact_sumsq_blocks(int n, int* rows) {
   return (n + R - 1) / R;
 }
 
+static constexpr size_t gemm64_lds() { return (size_t)4 * GM_K * GM_LD * sizeof(double); }
+
+// Opt the GEMM into more than 64 KB of dynamic LDS (two buffers of A and B slices).
+void gemm64_init() {
+  hipFuncSetAttribute((const void*)k_gemm64, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm64_lds());
+}
+
 void launch_gemm64(int n, const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                    double alpha, const double* D, int64_t ldd, double beta, hipStream_t s) {
+  static std::atomic<unsigned> ready{0};   // one bit per device: the LDS attribute is set
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 32 && !(ready.load() & (1u << dev))) {
+    gemm64_init();
+    ready.fetch_or(1u << dev);
+  }
   const int nt = (n + GM_B - 1) / GM_B;
-  hipLaunchKernelGGL(k_gemm64, dim3(nt, nt), dim3(GM_T), 0, s, n, A, lda, B, ldb, C, ldc, alpha, D, ldd, beta);
+  hipLaunchKernelGGL(k_gemm64, dim3(nt, nt), dim3(GM_T), gemm64_lds(), s, n, A, lda, B, ldb, C, ldc, alpha, D, ldd,
+                     beta);
 }
 
 void launch_ex_norm(int n, bool fp64, const void* X, int64_t ldx, double* part, double* out, psdproj_result* res,

@@ -354,9 +354,9 @@ __global__ __launch_bounds__(TD_THREADS) void k_tridiag(const Prob* __restrict__
     gu += slack + 1e-300;
     for (int i = 0; i + 1 < r; ++i) p.evals[PSDPROJ_MAX_RANK + i] = p.te[i] * p.te[i];  // e^2 scratch
     p.scal[S_TNORM] = tnorm;
-    p.scal[8] = gl;
-    p.scal[9] = gu;
-    p.scal[10] = pivmin;
+    p.scal[S_GL] = gl;
+    p.scal[S_GU] = gu;
+    p.scal[S_PIVMIN] = pivmin;
     const double thr = (p.variant == PSDPROJ_SCALED) ? 1.0 : 0.0;
     p.scal[S_THRESH] = thr;
     int nu = isfinite(tnorm) ? sturm_count(p.td, p.evals + PSDPROJ_MAX_RANK, r, thr, pivmin) : r;
