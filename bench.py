@@ -325,7 +325,9 @@ def main() -> int:
     flops_scaled = passes * 2 * nn * r + 2 * nn * r2.r_plus + 2 * (args.alpha_iters + 1) * 2 * nn
     bytes_plain = (passes + 1) * nn * es
     gk, gprod, gvec = alg5_products(args.alpha_iters)
-    bytes_scaled = bytes_plain + gprod * (n * (n + 1) / 2 * es + gvec * n)
+    # the method's algorithmic bytes: Alg. 5 as 2 (N + 1) products reading A in full, whatever
+    # the kernels actually read (the upper triangle once per product pair)
+    bytes_scaled = bytes_plain + 2 * (args.alpha_iters + 1) * nn * es
     step_s = ms_per_step / 1e3
     tflops = (flops_plain + flops_scaled) / step_s / 1e12
     gbs = (bytes_plain + bytes_scaled) / step_s / 1e9
