@@ -246,6 +246,7 @@ __global__ __launch_bounds__(256) void k_alpha2(const Prob* __restrict__ probs, 
   const int G = tstart[pi + 1] - tstart[pi];
   const int N = p.alpha_iters;
   __shared__ double cz[2][PAIRED_MAX + 2];
+  __shared__ double cw[2][PAIRED_MAX + 2];   // thread 0's coefficient vectors (no per-lane arrays)
   __shared__ double red[2][256 / WAVE];
   __shared__ double rows[2][256];
   __shared__ int is_last;
@@ -254,7 +255,8 @@ __global__ __launch_bounds__(256) void k_alpha2(const Prob* __restrict__ probs, 
   if (x == 0) {
     const double* rho = p.pw;
     const double* mu = p.pw + PAIRED_MAX + 2;
-    double c[PAIRED_MAX + 2], d[PAIRED_MAX + 2];
+    double* c = cw[0];
+    double* d = cw[1];
     for (int i = 0; i < N + 2; ++i) c[i] = 0.0;
     c[0] = 1.0;
     auto apply = [&]() {
