@@ -530,8 +530,9 @@ def main() -> int:
 
 def run_counters(args, dev) -> int:
     """The headline grouped step on a symmetric Gaussian matrix of the same size (the same kernels
-    and bytes; the generator avoids the QR that counter collection does not survive), then one
-    plain 1 GiB device-to-device copy whose FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    and bytes; the generator avoids the QR that counter collection does not survive), max(2,
+    steps / 10) times, then one plain 1 GiB device-to-device copy whose FETCH_SIZE / WRITE_SIZE
+    calibrate the counters."""
     import torch
     from paper_2410_19208_amd.torch_api import BatchProjector
     n, k, p, q = args.n, args.k, args.p, args.q
@@ -545,7 +546,7 @@ def run_counters(args, dev) -> int:
                                 alpha=0.0, alpha_iters=args.alpha_iters)], device=dev)
     P1 = torch.empty_like(A)
     P2 = torch.empty_like(A)
-    for _ in range(2):
+    for _ in range(max(2, args.steps // 10)):   # two steps by default; more to let the clock settle
         both([A, A], [P1, P2])
     torch.cuda.synchronize()
     src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
