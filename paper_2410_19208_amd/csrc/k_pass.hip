@@ -11,9 +11,11 @@
 // BF16X3 (k_pass_b3): v_mfma_f32_16x16x32_bf16 on the splits x = hi + lo (hi = bf16(x),
 // lo = bf16(x - hi)), accumulating hi*hi + hi*lo + lo*hi in FP32 (the lo*lo term, ~2^-16
 // relative, is dropped).  A is symmetric, so a tile's K slice is read as whole rows of A
-// (coalesced 1 KB rows), straight into registers in MFMA operand order and split there, two
-// steps ahead; Z is stored pre-split and its slices stream through a 3-slice LDS ring
-// (global_load_lds_dwordx4, no VGPR round trip).  8 waves x 32 rows x all r columns.
+// (coalesced 1 KB rows); Z is stored pre-split and its slices stream into LDS by DMA (no VGPR
+// round trip).  8 waves x 32 rows x all r columns.  Widths 10 .. 14 on 16-byte aligned rows
+// (pass_b3l_tile): A slices also reach LDS by DMA and are split from there, and the registers
+// this frees prefetch the MFMA B operands; other widths (pass_b3_tile) load A straight into
+// registers in MFMA operand order, two steps ahead.
 // FP32 (k_pass_f32): 8 waves own a 256-row tile and all r columns; each wave computes a
 // 64-row x r/2 block (4 x r/32 MFMA tiles).  Each K step of 32 moves the A slice (256 x 32)
 // and the Z slice (32 x r) from global memory straight into LDS, double-buffered, one
@@ -532,6 +534,245 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
   }
 }
 
+// ---------------------------------------------------------------- BF16X3, A through LDS
+// The same tile, product and virtual row blocks as pass_b3_tile on the 16-byte path, but the A
+// slice of a step reaches LDS by DMA (each wave copies 4 of its 32 rows, 1 KB each) instead of
+// through a ring of registers.  The registers that held A in flight prefetch the MFMA B operands
+// one column-block pair ahead instead, and each step's barrier sits before its last pair, so the
+// MFMAs of that pair run while the barrier clears and the next step's first operands are read.
+// A slices use a ring of 3 (rows padded to 1040 bytes, so the split's reads of rows 8 apart fall
+// in other banks), Z slices a ring of 2; both are copied right after a step's barrier and must
+// land by the next one.  The two rings take 157 KB at width 14 (width 16 does not fit).  Used
+// for widths 10 .. 14; measured at width 14, where the launch is about 3% shorter than with
+// pass_b3_tile (copying A two steps ahead instead of one gained nothing).
+// buffer range in bytes (a non-negative size), saturated to 32 bits
+__device__ __forceinline__ int nrec32(int64_t bytes) {
+  return (int)(((uint64_t)bytes >> 32) ? 0xffffffffu : (uint32_t)bytes);
+}
+constexpr int PBL_ROW = 1040;
+constexpr int PBL_ASLOT = PB_BK * PBL_ROW;
+__host__ __device__ constexpr bool pbl_used(int ncb) { return ncb >= 10 && ncb <= 14; }
+__host__ __device__ constexpr int pbl_lds_bytes(int ncb) { return 3 * PBL_ASLOT + 2 * pb_slice_bytes(ncb); }
+static_assert(pbl_lds_bytes(14) <= 160 * 1024, "both rings must fit the LDS of one CU");
+
+template <int NCB>
+__device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned char* smem) {
+  constexpr int VB = 2;
+  constexpr int NW = PASS_BM_F / (16 * VB);       // 8 waves
+  constexpr int SB = pb_slice_bytes(NCB);
+  constexpr int ZPW = (2 * NCB + NW - 1) / NW;    // Z blocks per wave and step
+  constexpr int APW = PB_BK / NW;                 // A rows per wave and step
+  const int s = t % p.split;
+  const int m0 = (t / p.split) * PASS_BM_F;
+  const int n = p.n, ld = p.ld;
+  const int kbeg = s * p.kchunk;
+  const int kend = max(kbeg, min(p.ktail, kbeg + p.kchunk));   // whole steps, all rows below n
+  const int nsteps = (kend - kbeg + PB_BK - 1) / PB_BK;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int li = lane & 15, kg = lane >> 4;
+  const gmem<const bf16>* __restrict__ zhi = gp((const bf16*)p.zhi);
+  const gmem<const bf16>* __restrict__ zlo = gp((const bf16*)p.zlo);
+  const int64_t lda = p.lda;
+  unsigned char* const aring = smem;
+  unsigned char* const zring = smem + 3 * PBL_ASLOT;
+
+  f32x4 acc[VB][NCB];
+#pragma unroll
+  for (int v = 0; v < VB; ++v)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[v][cb] = f32x4{0, 0, 0, 0};
+
+  // DMA of one A row: lane l copies columns m0 + 4l .. +3 (a group at or past n copies
+  // column 0 instead: its outputs are rows past n, never stored); the buffer starts at row k0
+  // and ends at A's last element, as in pass_b3_tile
+  const int ca = m0 + 4 * lane;
+  const uint32_t voff = (uint32_t)((ca < n ? ca : 0) * 4);
+  // A's base stays in scalar registers (otherwise the compiler reloads it from the descriptor
+  // every step, and the wait for that load also waits for the operand reads in flight)
+  const float* Ab = (const float*)p.A;
+  __asm__ volatile("" : "+s"(Ab));
+  const int lda4 = (int)(lda * 4);
+  // steps past the last one copy the last step again (into a slot nobody reads), so every step
+  // issues the same loads and the wait counts below stay exact
+  auto issue_a = [&](int slot, int st) {
+    const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Ab + (int64_t)k0 * lda), 0, nrec32(((int64_t)(n - 1 - k0) * lda + n) * 4), BUF_WORD3);
+    unsigned char* as = aring + slot * PBL_ASLOT;
+#pragma unroll
+    for (int u = 0; u < APW; ++u) {
+      const int row = wave + NW * u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(as + row * PBL_ROW), 16, voff, row * lda4, 0, BUF_NT);
+    }
+  };
+  // Z tile (k0 / 32, cb) of a split panel starts at element cb 16 ld + 16 k0 (see pass_b3_tile).
+  // One buffer covers both split panels (two regions of the same workspace): it starts at
+  // element 16 k0 of the lower one, block b of a step is a fixed scalar offset (the panel's
+  // distance from the base plus cb 16 ld elements), and every lane copies its 16 bytes at the
+  // same lane offset.
+  const uint32_t zvoff = (uint32_t)lane << 4;
+  const char* const zbase = ((const char*)p.zhi < (const char*)p.zlo) ? (const char*)p.zhi : (const char*)p.zlo;
+  const int64_t zspan = max((const char*)p.zhi, (const char*)p.zlo) - zbase + (int64_t)p.rpad * ld * 2;
+  int zsoff[ZPW];
+#pragma unroll
+  for (int u = 0; u < ZPW; ++u) {
+    const int b = (wave + NW * u) % (2 * NCB);
+    const char* panel = (b < NCB) ? (const char*)p.zhi : (const char*)p.zlo;
+    zsoff[u] = (int)(panel - zbase) + ((b < NCB) ? b : b - NCB) * 32 * ld;
+  }
+  auto issue_z = [&](int slot, int st) {
+    const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(zbase + 32 * (int64_t)k0), 0, nrec32(zspan - 32 * (int64_t)k0), BUF_WORD3);
+    unsigned char* zs = zring + slot * SB;
+#pragma unroll
+    for (int u = 0; u < ZPW; ++u) {
+      const int b = (wave + NW * u) % (2 * NCB);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(zs + b * 1024), 16, zvoff, zsoff[u], 0, 0);
+    }
+  };
+
+  // Step st runs in register set R = st mod 2 and reads Z slot R.  Its column-block pairs run
+  // 12 MFMAs each while the B operands of the next pair are read.  With pair SP, the A values of
+  // step st + 1 are read from LDS and split into the other register set.  Lane (li, kg) takes
+  // rows 8kg .. 8kg+7 of the slice at columns 32 wave + 2 li, +1: virtual row blocks 0 and 1.
+  // The step's barrier comes before its last pair.  By then this wave's copies of the Z slice of
+  // step st + 1 and the A slice of step st + 2 have landed, and its reads of step st's Z slot and
+  // of A(st + 1) are done.  After the barrier the wave copies the Z slice of step st + 2 into
+  // slot R and the A slice of step st + 3 into the slot of A(st).  It then reads the first B
+  // operands of step st + 1 while the last pair's MFMAs run, so no wave stands idle after the
+  // barrier.  The scheduling groups fix this order (the default schedule reads each pair's
+  // operands just before its MFMAs and waits for them).
+  constexpr int NP = NCB / 2;
+  constexpr int SP = NP / 2 - 1;
+  bf16x8 ahi[2][VB], alo[2][VB];
+  bf16x8 b[2][4];
+  const int aoff = 8 * kg * PBL_ROW + (32 * wave + 2 * li) * 4;
+  const int zoff = lane << 4;
+  auto bread = [&](bf16x8 (&d)[4], const unsigned char* zs, int cb) {
+    d[0] = *(const bf16x8*)(zs + cb * 1024);
+    d[1] = *(const bf16x8*)(zs + (cb + 1) * 1024);
+    d[2] = *(const bf16x8*)(zs + (NCB + cb) * 1024);
+    d[3] = *(const bf16x8*)(zs + (NCB + cb + 1) * 1024);
+  };
+  auto pair = [&](auto R_, const bf16x8 (&bb)[4], int cb) {
+    constexpr int R = decltype(R_)::value;
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[R][v], bb[0], acc[v][cb], 0, 0, 0);
+      acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[R][v], bb[1], acc[v][cb + 1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[R][v], bb[2], acc[v][cb], 0, 0, 0);
+      acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[R][v], bb[3], acc[v][cb + 1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      acc[v][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[R][v], bb[0], acc[v][cb], 0, 0, 0);
+      acc[v][cb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[R][v], bb[1], acc[v][cb + 1], 0, 0, 0);
+    }
+  };
+  // pair j of a step in register set R uses operand buffer (j + R NP) mod 2, so the first pair of
+  // the next step never shares a buffer with the last pair of this one
+  auto step = [&](auto R_, int st, int a_issue, int a_next) {
+    constexpr int R = decltype(R_)::value;
+    const unsigned char* zs = zring + R * SB + zoff;
+    const unsigned char* as = aring + a_next * PBL_ASLOT + aoff;
+    f32x2 xa[8];
+#pragma unroll
+    for (int j = 0; j < NP - 1; ++j) {
+      const int c = (j + R * NP) & 1;
+      bread(b[c ^ 1], zs, 2 * j + 2);
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+      if (j == SP) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xa[e] = *(const f32x2*)(as + e * PBL_ROW);
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+      }
+      pair(R_, b[c], 2 * j);
+      __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
+      if (j == SP) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int v = 0; v < VB; ++v) {
+            const bf16 hb = (bf16)xa[e][v];
+            ahi[1 - R][v][e] = hb;
+            alo[1 - R][v][e] = (bf16)(xa[e][v] - (float)hb);
+          }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(PB_VMCNT(0));
+    __asm__ volatile("s_barrier" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    issue_z(R, st + 2);
+    issue_a(a_issue, st + 3);
+    constexpr int cl = (NP - 1 + R * NP) & 1;
+    bread(b[cl ^ 1], zring + (1 - R) * SB + zoff, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 1);
+    pair(R_, b[cl], 2 * (NP - 1));
+    __builtin_amdgcn_sched_group_barrier(0x008, 12, 1);
+  };
+
+  using R0 = std::integral_constant<int, 0>;
+  using R1 = std::integral_constant<int, 1>;
+  // a chunk that ktail leaves empty (nsteps = 0) copies the step before it, whose rows are below
+  // n (kbeg >= 64), and writes a zero partial tile
+  issue_a(0, 0);
+  issue_a(1, 1);
+  issue_a(2, 2);
+  issue_z(0, 0);
+  issue_z(1, 1);
+  __builtin_amdgcn_s_waitcnt(PB_VMCNT(0));
+  __asm__ volatile("s_barrier" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+  {
+    const unsigned char* as = aring + aoff;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const f32x2 x = *(const f32x2*)(as + e * PBL_ROW);
+#pragma unroll
+      for (int v = 0; v < VB; ++v) {
+        const bf16 hb = (bf16)x[v];
+        ahi[0][v][e] = hb;
+        alo[0][v][e] = (bf16)(x[v] - (float)hb);
+      }
+    }
+    bread(b[0], zring + zoff, 0);
+  }
+  int st = 0, a0 = 0;   // a0 = st mod 3: the A slot of step st
+  for (; st + 2 <= nsteps; st += 2) {
+    const int a1 = (a0 == 2) ? 0 : a0 + 1, a2 = (a1 == 2) ? 0 : a1 + 1;
+    step(R0{}, st, a0, a1);
+    step(R1{}, st + 1, a1, a2);
+    a0 = a2;
+  }
+  if (st < nsteps) step(R0{}, st, a0, (a0 == 2) ? 0 : a0 + 1);
+  // the copies of the steps past the end must land before the workgroup's LDS is freed
+  __builtin_amdgcn_s_waitcnt(PB_VMCNT(0));
+
+  // ---- partial tile (same lane layout as pass_b3_tile)
+  float* __restrict__ out = (float*)p.part + (int64_t)s * p.rpad * ld;
+  const int rbase = m0 + 16 * VB * wave + 4 * VB * kg;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    float vals[4 * VB];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int v = 0; v < VB; ++v) vals[VB * r + v] = acc[v][cb][r];
+    float* col = out + (int64_t)(cb * 16 + li) * ld + rbase;
+#pragma unroll
+    for (int h = 0; h < VB; ++h)
+      if (rbase + 4 * h < n) *(f32x4*)(col + 4 * h) = f32x4{vals[4 * h], vals[4 * h + 1], vals[4 * h + 2], vals[4 * h + 3]};
+  }
+}
+
+__host__ __device__ constexpr int pb_kernel_lds(int ncb) {
+  return (pbl_used(ncb) && pbl_lds_bytes(ncb) > pb_lds_bytes(ncb)) ? pbl_lds_bytes(ncb) : pb_lds_bytes(ncb);
+}
+
 template <int NCB, int VB>
 __global__ __launch_bounds__(PASS_BM_F / (16 * VB) * 64, 1)
 void k_pass_b3(const Prob* __restrict__ probs, const int* __restrict__ tstart, int nprob) {
@@ -552,8 +793,12 @@ void k_pass_b3(const Prob* __restrict__ probs, const int* __restrict__ tstart, i
   }
   const Prob& p = probs[pi];
   if (t >= p.npass_tiles) return;
-  if (p.avec) pass_b3_tile<NCB, VB, true>(p, t, smem);
-  else pass_b3_tile<NCB, VB, false>(p, t, smem);
+  if (p.avec) {
+    if constexpr (pbl_used(NCB) && VB == 2) pass_b3l_tile<NCB>(p, t, smem);
+    else pass_b3_tile<NCB, VB, true>(p, t, smem);
+  } else {
+    pass_b3_tile<NCB, VB, false>(p, t, smem);
+  }
 }
 
 // Y = sum_s part[s] in fixed order; scaled: Y = (Y + alpha Z) / alpha.  Zero outside n x r.
@@ -637,7 +882,7 @@ void launch_pass(const Launch& L, int prec, int ncb) {
                          L.probs, L.tstart, L.nprob);                                                            \
     else                                                                                                         \
       hipLaunchKernelGGL((k_pass_b3<N, PB_VB>), dim3(L.grid), dim3(PASS_BM_F / (16 * PB_VB) * 64),               \
-                         pb_lds_bytes(N), L.stream,                                                              \
+                         pb_kernel_lds(N), L.stream,                                                             \
                          L.probs, L.tstart, L.nprob);                                                            \
     break;
     PSD_NCB_EVEN(PSD_CASE)
@@ -652,7 +897,7 @@ void pass_init() {
   hipFuncSetAttribute((const void*)k_pass_f32<N>, hipFuncAttributeMaxDynamicSharedMemorySize,   \
                       2 * pl_stage_bytes(N));                                                          \
   hipFuncSetAttribute((const void*)k_pass_b3<N, PB_VB>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
-                      pb_lds_bytes(N));
+                      pb_kernel_lds(N));
   PSD_NCB_EVEN(PSD_ATTR)
 #undef PSD_ATTR
 }

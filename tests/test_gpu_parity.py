@@ -214,11 +214,12 @@ def test_batch_equals_single_runs_bitwise():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("k,p", [(170, 10), (210, 10), (240, 10), (246, 10)])
+@pytest.mark.parametrize("k,p", [(140, 10), (170, 10), (210, 10), (240, 10), (246, 10)])
 def test_parity_wide_panels(prec, k, p):
-    """Sketch widths r = 180, 220, 250, 256 (padded widths 192, 224, 256, 256): the widest
-    register-tiled forms of the pass, Cholesky, apply and tridiagonalisation kernels, both
-    variants (alpha estimated by Alg. 5), one power step."""
+    """Sketch widths r = 150, 180, 220, 250, 256 (padded widths 160, 192, 224, 256, 256): the
+    widest register-tiled forms of the pass, Cholesky, apply and tridiagonalisation kernels (for
+    BF16X3 the widths 160 .. 224 take the pass whose A slices go through LDS), both variants
+    (alpha estimated by Alg. 5), one power step."""
     n, q = 1500, 1
     A, lam, U = matrix("medium", n, 11, n_pos=300)
     for variant in ("plain", "scaled"):
@@ -232,6 +233,24 @@ def test_parity_wide_panels(prec, k, p):
         print(f"wide r={k + p} {prec} {variant}: parity {err:.3e} r+ {res.r_plus}")
         assert err < TOL[prec]
         assert np.array_equal(P, P.T)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("k,p", [(150, 10), (190, 10)])
+def test_parity_empty_k_chunk(prec, k, p):
+    """n = 260: the pass splits K into chunks of 128 rows (0, 128, 256), and the 16-byte BF16X3
+    pass covers whole 32-row steps only (rows below 256), so its third chunk has no step: it
+    must write a zero partial tile while rows 256 .. 259 come from the reduction.  Widths 160
+    and 224, both variants, one power step."""
+    n, q = 260, 1
+    A, lam, U = matrix("medium", n, 12, n_pos=60)
+    for variant in ("plain", "scaled"):
+        proj, P, res = run_gpu(A, k, p, q, variant, prec, seed=8)
+        ref = run_oracle(A, k, p, q, variant, prec, seed=8)
+        assert res.status == 0 and res.r_plus == ref.r_plus
+        err = parity(P, ref, A)
+        print(f"n=260 r={k + p} {prec} {variant}: parity {err:.3e}")
+        assert err < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
