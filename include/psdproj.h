@@ -287,8 +287,9 @@ psdproj_status psdproj_sdls_solve(const psdproj_sdls_desc* desc, const void* C, 
  * admitted in FIFO order while their workspaces fit in it and fewer than max_inflight are in
  * flight.  The budget covers only the memory the server itself allocates: A and P are
  * caller-owned buffers that exist before submit and stay allocated whether or not a request
- * is admitted, so admitting or deferring a request changes nothing in their footprint; each admission round becomes one grouped launch sequence (as psdproj_batch) on one
- * of two server streams, and arrivals join at the next round.  A and P stay caller-owned and
+ * is admitted, so admitting or deferring a request changes nothing in their footprint.  Each
+ * admission round becomes one grouped launch sequence (as psdproj_batch) on a free one of four
+ * server streams, and arrivals join at the next round.  A and P stay caller-owned and
  * must stay valid until the ticket completes.  Each request's P is bitwise identical to a
  * psdproj_run of the same desc.  submit validates synchronously (E_INVALID; E_BUDGET when the
  * request alone exceeds the budget); a device failure of a batch is reported in the status
