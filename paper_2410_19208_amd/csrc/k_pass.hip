@@ -536,14 +536,14 @@ __device__ __forceinline__ void pass_b3_tile(const Prob& p, int t, unsigned char
 
 // ---------------------------------------------------------------- BF16X3, A through LDS
 // The same tile, product and virtual row blocks as pass_b3_tile on the 16-byte path, but the A
-// slice of a step reaches LDS by DMA (each wave copies 4 of its 32 rows, 1 KB each) instead of
-// through a ring of registers.  The registers that held A in flight prefetch the MFMA B operands
-// one column-block pair ahead instead, and each step's barrier sits before its last pair, so the
-// MFMAs of that pair run while the barrier clears and the next step's first operands are read.
-// A slices use a ring of 3 (rows padded to 1040 bytes, so the split's reads of rows 8 apart fall
-// in other banks), Z slices a ring of 2; both are copied right after a step's barrier and must
-// land by the next one.  The two rings take 157 KB at width 14 (width 16 does not fit).  Used
-// for widths 10 .. 14; measured at width 14, where the launch is about 3% shorter than with
+// slice of a step reaches LDS by DMA (1 KB rows) instead of through a ring of registers.  The
+// registers that held A in flight prefetch the MFMA B operands one column-block pair ahead
+// instead, and each step's barrier sits before its last pair, so the MFMAs of that pair run while
+// the barrier clears and the next step's first operands are read.  A slices use a ring of 3 (rows
+// padded to 1040 bytes, so the split's reads of rows 8 apart fall in other banks), Z slices a
+// ring of 2; both are copied right after a step's barrier, by one wave per SIMD only, and must
+// land by the next barrier.  The two rings take 157 KB at width 14 (width 16 does not fit).
+// Used for widths 10 .. 14; measured at width 14, where the launch is about 7% shorter than with
 // pass_b3_tile (copying A two steps ahead instead of one gained nothing).
 // buffer range in bytes (a non-negative size), saturated to 32 bits
 __device__ __forceinline__ int nrec32(int64_t bytes) {
@@ -560,8 +560,13 @@ __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned cha
   constexpr int VB = 2;
   constexpr int NW = PASS_BM_F / (16 * VB);       // 8 waves
   constexpr int SB = pb_slice_bytes(NCB);
-  constexpr int ZPW = (2 * NCB + NW - 1) / NW;    // Z blocks per wave and step
-  constexpr int APW = PB_BK / NW;                 // A rows per wave and step
+  // Only waves 0 .. 3, one per SIMD, copy slices: a wave that issues a burst of copies stalls
+  // until the vector memory unit has taken them (about 1 KB per instruction), so with the
+  // copies in one wave of each SIMD the other wave keeps the matrix core busy meanwhile.
+  constexpr int DW = 4;                           // copying waves
+  constexpr int ZPC = 2 * NCB / DW;               // Z blocks per copying wave and step
+  constexpr int APC = PB_BK / DW;                 // A rows per copying wave and step
+  static_assert((2 * NCB) % DW == 0, "Z blocks split evenly over the copying waves");
   const int s = t % p.split;
   const int m0 = (t / p.split) * PASS_BM_F;
   const int n = p.n, ld = p.ld;
@@ -570,8 +575,7 @@ __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned cha
   const int nsteps = (kend - kbeg + PB_BK - 1) / PB_BK;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int li = lane & 15, kg = lane >> 4;
-  const gmem<const bf16>* __restrict__ zhi = gp((const bf16*)p.zhi);
-  const gmem<const bf16>* __restrict__ zlo = gp((const bf16*)p.zlo);
+  const bool copier = wave < DW;
   const int64_t lda = p.lda;
   unsigned char* const aring = smem;
   unsigned char* const zring = smem + 3 * PBL_ASLOT;
@@ -582,7 +586,7 @@ __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned cha
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[v][cb] = f32x4{0, 0, 0, 0};
 
-  // DMA of one A row: lane l copies columns m0 + 4l .. +3 (a group at or past n copies
+  // copy of one A row: lane l copies columns m0 + 4l .. +3 (a group at or past n copies
   // column 0 instead: its outputs are rows past n, never stored); the buffer starts at row k0
   // and ends at A's last element, as in pass_b3_tile
   const int ca = m0 + 4 * lane;
@@ -595,13 +599,14 @@ __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned cha
   // steps past the last one copy the last step again (into a slot nobody reads), so every step
   // issues the same loads and the wait counts below stay exact
   auto issue_a = [&](int slot, int st) {
+    if (!copier) return;
     const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(Ab + (int64_t)k0 * lda), 0, nrec32(((int64_t)(n - 1 - k0) * lda + n) * 4), BUF_WORD3);
     unsigned char* as = aring + slot * PBL_ASLOT;
 #pragma unroll
-    for (int u = 0; u < APW; ++u) {
-      const int row = wave + NW * u;
+    for (int u = 0; u < APC; ++u) {
+      const int row = wave + DW * u;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(as + row * PBL_ROW), 16, voff, row * lda4, 0, BUF_NT);
     }
   };
@@ -613,21 +618,22 @@ __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned cha
   const uint32_t zvoff = (uint32_t)lane << 4;
   const char* const zbase = ((const char*)p.zhi < (const char*)p.zlo) ? (const char*)p.zhi : (const char*)p.zlo;
   const int64_t zspan = max((const char*)p.zhi, (const char*)p.zlo) - zbase + (int64_t)p.rpad * ld * 2;
-  int zsoff[ZPW];
+  int zsoff[ZPC];
 #pragma unroll
-  for (int u = 0; u < ZPW; ++u) {
-    const int b = (wave + NW * u) % (2 * NCB);
+  for (int u = 0; u < ZPC; ++u) {
+    const int b = wave % DW + DW * u;
     const char* panel = (b < NCB) ? (const char*)p.zhi : (const char*)p.zlo;
     zsoff[u] = (int)(panel - zbase) + ((b < NCB) ? b : b - NCB) * 32 * ld;
   }
   auto issue_z = [&](int slot, int st) {
+    if (!copier) return;
     const int k0 = kbeg + min(st, nsteps - 1) * PB_BK;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)(zbase + 32 * (int64_t)k0), 0, nrec32(zspan - 32 * (int64_t)k0), BUF_WORD3);
     unsigned char* zs = zring + slot * SB;
 #pragma unroll
-    for (int u = 0; u < ZPW; ++u) {
-      const int b = (wave + NW * u) % (2 * NCB);
+    for (int u = 0; u < ZPC; ++u) {
+      const int b = wave + DW * u;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(zs + b * 1024), 16, zvoff, zsoff[u], 0, 0);
     }
   };
