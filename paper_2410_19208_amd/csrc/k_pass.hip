@@ -557,8 +557,7 @@ static_assert(pbl_lds_bytes(14) <= 160 * 1024, "both rings must fit the LDS of o
 
 template <int NCB>
 __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned char* smem) {
-  constexpr int VB = 2;
-  constexpr int NW = PASS_BM_F / (16 * VB);       // 8 waves
+  constexpr int VB = 2;                           // 8 waves of 32 rows
   constexpr int SB = pb_slice_bytes(NCB);
   // Only waves 0 .. 3, one per SIMD, copy slices: a wave that issues a burst of copies stalls
   // until the vector memory unit has taken them (about 1 KB per instruction), so with the
@@ -642,12 +641,12 @@ __device__ __forceinline__ void pass_b3l_tile(const Prob& p, int t, unsigned cha
   // 12 MFMAs each while the B operands of the next pair are read.  With pair SP, the A values of
   // step st + 1 are read from LDS and split into the other register set.  Lane (li, kg) takes
   // rows 8kg .. 8kg+7 of the slice at columns 32 wave + 2 li, +1: virtual row blocks 0 and 1.
-  // The step's barrier comes before its last pair.  By then this wave's copies of the Z slice of
-  // step st + 1 and the A slice of step st + 2 have landed, and its reads of step st's Z slot and
-  // of A(st + 1) are done.  After the barrier the wave copies the Z slice of step st + 2 into
-  // slot R and the A slice of step st + 3 into the slot of A(st).  It then reads the first B
-  // operands of step st + 1 while the last pair's MFMAs run, so no wave stands idle after the
-  // barrier.  The scheduling groups fix this order (the default schedule reads each pair's
+  // The step's barrier comes before its last pair.  By then the copies of the Z slice of step
+  // st + 1 and the A slice of step st + 2 have landed (each copying wave waits for its own), and
+  // every wave's reads of step st's Z slot and of A(st + 1) are done.  After the barrier waves
+  // 0 .. 3 copy the Z slice of step st + 2 into slot R and the A slice of step st + 3 into the
+  // slot of A(st).  Every wave then reads the first B operands of step st + 1 while the last
+  // pair's MFMAs run, so no wave stands idle after the barrier.  The scheduling groups fix this order (the default schedule reads each pair's
   // operands just before its MFMAs and waits for them).
   constexpr int NP = NCB / 2;
   constexpr int SP = NP / 2 - 1;
