@@ -160,6 +160,9 @@ Prob make_prob(const Plan& pl, unsigned char* region, const void* A, int64_t lda
   // the 16-byte BF16X3 pass reads whole 32-row steps of A, all below n; the partial step's rows
   // are added by the pass reduction (n < 32: the element path)
   if (pl.prec == B3 && d.n < 32) p.avec = 0;
+  // the 16-byte paths address up to 32 rows of A by 32-bit byte offsets from a per-step base;
+  // longer rows take the element paths (64-bit addresses)
+  if (lda > (int64_t(1) << 24)) p.avec = 0;
   p.ktail = (pl.prec == B3 && p.avec) ? (int)(d.n - d.n % 32) : (int)d.n;
   p.sketch = (d.flags & PSDPROJ_FLAG_SRHT) ? 1 : 0;
   p.csr = pl.csr;

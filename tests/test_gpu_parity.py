@@ -253,6 +253,35 @@ def test_parity_empty_k_chunk(prec, k, p):
         assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_huge_row_stride(prec):
+    """Rows 2^24 + 64 elements apart (an n x n view into a 13 GB buffer): the 16-byte paths,
+    which reach 32 rows of A by 32-bit byte offsets from a per-step base, must give way to the
+    element paths (width 160 would otherwise take the BF16X3 pass whose A slices go through LDS).
+    Both variants, one power step, against the oracle."""
+    import torch
+    from paper_2410_19208_amd.torch_api import Projector
+    n, k, p, q = 200, 150, 10, 1
+    lda = (1 << 24) + 64
+    A, lam, U = matrix("medium", n, 13, n_pos=40)
+    dev = _gpu.device()
+    buf = torch.empty((n - 1) * lda + n, dtype=torch.float32, device=dev)
+    At = torch.as_strided(buf, (n, n), (lda, 1))
+    At.copy_(torch.from_numpy(A.astype(np.float32)).to(dev))
+    for variant in ("plain", "scaled"):
+        proj = Projector(n, k, p, q, variant, prec, seed=9, device=dev)
+        P = proj(At)
+        torch.cuda.synchronize()
+        res = proj.result()
+        ref = run_oracle(A, k, p, q, variant, prec, seed=9)
+        assert res.status == 0 and res.r_plus == ref.r_plus
+        err = parity(P.cpu().numpy(), ref, A)
+        print(f"lda=2^24+64 {prec} {variant}: parity {err:.3e}")
+        assert err < TOL[prec]
+    del At, buf
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_cor2_repeated_eigenvalues(prec):
     """The matrix class of Cor. 2 (four blocks of n/4 equal eigenvalues -3, -1, 6, 2), n = 512,
