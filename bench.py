@@ -55,8 +55,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_large_20k_bf16x3.md")
 def measured_traffic(kernel: str, problems_per_launch: float):
     """HBM bytes per launch (read + written) of `kernel` from the counter summary in profiles/:
     FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy.  None when there is no entry, when the
-    launch covers a different number of problems, or when the kernel's source has changed
-    since the counters were taken."""
+    launch covers a different number of problems, or when the kernel's source, or a file that
+    shapes its launch (the entry's "also" list, e.g. the split-K table), has changed since the
+    counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -64,9 +65,10 @@ def measured_traffic(kernel: str, problems_per_launch: float):
         ent = json.loads(block).get(kernel)
         if ent is None or abs(ent["problems_per_launch"] - problems_per_launch) > 1e-9:
             return None
-        with open(os.path.join(ROOT, ent["source"]), "rb") as f:
-            if hashlib.sha1(f.read()).hexdigest() != ent["sha1"]:
-                return None
+        for src, digest in [(ent["source"], ent["sha1"])] + [tuple(x) for x in ent.get("also", [])]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                if hashlib.sha1(f.read()).hexdigest() != digest:
+                    return None
         return float(ent["read_bytes"] + ent["write_bytes"])
     except (OSError, IndexError, ValueError, KeyError):
         return None
