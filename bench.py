@@ -100,10 +100,13 @@ def parse():
                     help="skip the untimed single-request, one-in-flight and sequential/grouped comparison "
                          "timings (profiler runs: only the warmup, kernel-table and timed steps launch "
                          "kernels, all with --inflight steps in flight)")
-    ap.add_argument("--inflight", type=int, default=3,
+    ap.add_argument("--inflight", type=int, default=None,
                     help="steps in flight: consecutive steps go round-robin to this many HIP streams, each "
                          "with its own workspace and outputs, so one step's latency-bound eigensolve "
-                         "overlaps the next step's streaming kernels (1: one stream)")
+                         "overlaps the next steps' streaming kernels (1: one stream).  Default 3 for the "
+                         "dense step (4 gives 1-2%% more projections/s, but the pass's launches then "
+                         "overlap more and each takes longer), 4 for the sparse and structured-sketch "
+                         "modes (4 matches the hardware queues HIP gives a process)")
     ap.add_argument("--sequential", action="store_true",
                     help="time the step as two psdproj_run calls instead of one grouped psdproj_batch")
     ap.add_argument("--mode", default="step",
@@ -119,7 +122,10 @@ def parse():
     ap.add_argument("--qps", default="50,100,200,500,1000,2000", help="serve mode: arrival rates")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests per arrival rate (at most) in serve mode and in the serving leg of the step")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.inflight is None:
+        args.inflight = 4 if args.mode in ("sparse", "sketch") else 3
+    return args
 
 
 def main() -> int:

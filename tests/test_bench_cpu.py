@@ -48,6 +48,24 @@ def test_traffic_figure_needs_matching_source_and_problem_count(tmp_path, monkey
     assert bench.measured_traffic("k_x", 2.0) is None
 
 
+def test_traffic_figure_needs_matching_launch_files(tmp_path, monkeypatch):
+    # the pass's figures also depend on the split-K table that shapes its launch
+    import hashlib
+    src = tmp_path / "kernel.hip"
+    src.write_text("// kernel source\n")
+    table = tmp_path / "table.inc"
+    table.write_text("{2, 14, 224, 4},\n")
+    entry = {"source": str(src), "sha1": hashlib.sha1(src.read_bytes()).hexdigest(),
+             "also": [[str(table), hashlib.sha1(table.read_bytes()).hexdigest()]],
+             "problems_per_launch": 2, "read_bytes": 1000, "write_bytes": 24}
+    summary = tmp_path / "traffic.md"
+    summary.write_text(_summary_with({"k_x": entry}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(summary))
+    assert bench.measured_traffic("k_x", 2.0) == 1024.0
+    table.write_text("{2, 14, 224, 8},\n")
+    assert bench.measured_traffic("k_x", 2.0) is None
+
+
 def test_committed_summary_parses():
     # every committed entry either applies to the current source or is skipped, never an error
     for kernel, ppl in (("k_pass", 2.0), ("k_gemv", 1.0), ("k_rebuild", 2.0)):
