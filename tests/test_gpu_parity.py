@@ -253,6 +253,23 @@ def test_parity_empty_k_chunk(prec, k, p):
         assert err < TOL[prec]
 
 
+@pytest.mark.parametrize("n", [160, 192])
+def test_parity_short_k_chunks(n):
+    """n = 160 and 192 at width 160 (k + p = 150): two K chunks of 128 rows, the second holding
+    one or two 32-row steps of the 16-byte BF16X3 pass (whose A slices go through LDS), so the
+    copies issued ahead of the first step reach past the chunk's last step.  Both variants, one
+    power step."""
+    k, p, q = 140, 10, 1
+    A, lam, U = matrix("medium", n, 14, n_pos=30)
+    for variant in ("plain", "scaled"):
+        proj, P, res = run_gpu(A, k, p, q, variant, "bf16x3", seed=10)
+        ref = run_oracle(A, k, p, q, variant, "bf16x3", seed=10)
+        assert res.status == 0 and res.r_plus == ref.r_plus
+        err = parity(P, ref, A)
+        print(f"n={n} r=150 bf16x3 {variant}: parity {err:.3e}")
+        assert err < TOL["bf16x3"]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_huge_row_stride(prec):
     """Rows 2^24 + 64 elements apart (an n x n view into a 13 GB buffer): the 16-byte paths,
