@@ -362,3 +362,22 @@ def test_exact_clusters_recovered():
     assert res.status == 0 and res.r_plus >= 80
     assert parity(P, ref, A) < TOL["fp64"]
     assert np.linalg.norm(P - Ap) / np.linalg.norm(Ap) < 1e-11
+
+
+@pytest.mark.parametrize("variant", ["plain", "scaled"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_negative_definite_projects_to_zero(prec, variant):
+    # Every Ritz value of a negative definite matrix is negative, so neither clamp keeps a
+    # direction (Alg. 2: max(d, 0); Alg. 3: max(d, 1) - 1 with d = lambda / alpha + 1 < 1):
+    # r_plus = 0 on both sides and the rebuild writes P = 0 exactly.
+    n = 300
+    rng = np.random.default_rng(23)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = -rng.uniform(0.1, 1.0, n)
+    A = (U * lam) @ U.T
+    A = 0.5 * (A + A.T)
+    proj, P, res = run_gpu(A, 20, 10, 1, variant, prec, seed=5, alpha=0.0)
+    ref = run_oracle(A, 20, 10, 1, variant, prec, seed=5, keep_P=False)
+    assert res.status == 0
+    assert res.r_plus == 0 and ref.r_plus == 0
+    assert not P.any()

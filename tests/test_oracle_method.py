@@ -206,6 +206,18 @@ def test_output_symmetric_psd_idempotent():
     assert np.linalg.norm(P2 - P) < 1e-11 * np.linalg.norm(P)
 
 
+@pytest.mark.parametrize("variant", ["plain", "scaled"])
+def test_negative_definite_projects_to_zero(variant):
+    """X negative definite: X_+ = 0, and every Ritz value is negative, so the clamps of Alg. 2
+    (max(d, 0)) and Alg. 3 (max(d, 1) - 1 with d = lambda/alpha + 1 < 1) keep nothing."""
+    lam = -np.linspace(0.1, 1.0, 120)
+    X, _ = sym_from(lam, 31)
+    res = rnla.project(X, 15, 10, 1, variant, seed=6)
+    assert res.r_plus == 0
+    assert not res.P.any()
+    assert np.all(res.evals < (1.0 if variant == "scaled" else 0.0))
+
+
 def test_obtuse_angle_inequality():
     """Projection onto the convex PSD cone: ||X_+ - P||^2 <= ||X - P||^2 - ||X - X_+||^2 for PSD P."""
     lam = workloads.spectrum_medium(120, 20, 10)

@@ -62,6 +62,8 @@ PINS = {
     "plain_recovery_q1": lambda: TM.test_plain_exact_recovery_low_rank(1),
     "scaled_recovery": lambda: TM.test_scaled_exact_recovery(),
     "full_width": lambda: TM.test_full_width_is_exact(),
+    "neg_def_plain": lambda: TM.test_negative_definite_projects_to_zero("plain"),
+    "neg_def_scaled": lambda: TM.test_negative_definite_projects_to_zero("scaled"),
     "min_eig_case1": lambda: TM.test_min_eig_lemma([1.0, 0.5, -2.0, -4.0], 4.0),
     "min_eig_case2": lambda: TM.test_min_eig_lemma([5.0, 4.0, 1.0, -0.5, -3.0], 3.0),
     "power_rate": lambda: TM.test_power_iteration_rate(),
@@ -89,13 +91,13 @@ PINS = {
 # (id, oracle file, text, replacement, pins expected to notice)
 MUTANTS = [
     ("plain_no_clamp", "rnla.py", "weights = np.maximum(evals, 0.0)", "weights = evals.copy()",
-     ["cex1_plain_vs_scaled", "plain_compressed_q1"]),
+     ["cex1_plain_vs_scaled", "plain_compressed_q1", "neg_def_plain"]),
     ("plain_clamp_sign", "rnla.py", "weights = np.maximum(evals, 0.0)", "weights = np.maximum(-evals, 0.0)",
-     ["cex1_plain_vs_scaled", "plain_compressed_q1", "plain_recovery_q1"]),
+     ["cex1_plain_vs_scaled", "plain_compressed_q1", "plain_recovery_q1", "neg_def_plain"]),
     ("scaled_drops_alpha", "rnla.py", "alpha * (np.maximum(evals, 1.0) - 1.0)", "(np.maximum(evals, 1.0) - 1.0)",
      ["lemma3", "scaled_recovery", "full_width"]),
     ("scaled_threshold_zero", "rnla.py", "alpha * (np.maximum(evals, 1.0) - 1.0)", "alpha * np.maximum(evals, 0.0)",
-     ["lemma3", "scaled_recovery", "full_width"]),
+     ["lemma3", "scaled_recovery", "full_width", "neg_def_scaled"]),
     ("B_shift_sign", "rnla.py", "(np.diag(X) + alpha) / alpha", "(np.diag(X) - alpha) / alpha",
      ["lemma3", "cex1_plain_vs_scaled", "scaled_recovery"]),
     ("B_not_scaled", "rnla.py", "B = X / alpha  ", "B = X.copy()  ",
