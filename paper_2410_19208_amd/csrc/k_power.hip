@@ -339,9 +339,10 @@ __global__ __launch_bounds__(256) void k_alpha2(const Prob* __restrict__ probs, 
   }
 }
 
-// Stream one wave's 64 rows of a tile in batches of RB rows, double-buffered in registers (the
-// loop is fully unrolled, so the loads of batch bt+1 are in flight while batch bt is used and
-// no copy between the buffers forces an early wait), against NV vectors at once (one element
+// Stream one wave's 64 rows of a tile in batches of RB rows, NBUF of them in flight in register
+// buffers (the loop is fully unrolled, so the loads of batches bt+1 .. bt+NBUF-1 are in flight
+// while batch bt is used and no copy between the buffers forces an early wait; the arithmetic
+// and its order do not depend on NBUF), against NV vectors at once (one element
 // of A read, NV row and NV column terms formed).  VEC: rows start and end 16-byte aligned,
 // so a 16-byte chunk lies wholly inside or wholly past column n; chunks past n read the row's
 // first chunk instead (their v_J entries are zero, and their column sums belong to columns
@@ -357,7 +358,10 @@ __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A,
                                             int lane) {
   constexpr int NBT = 64 / RB;
   constexpr int LOGRB = (RB == 16) ? 4 : (RB == 8) ? 3 : 2;
-  T a[2][RB][4];
+  // batches in flight: three for two vectors (the products' 2 waves per SIMD have registers for
+  // a third buffer), two for one vector (3 waves per SIMD)
+  constexpr int NBUF = (NV == 2 && sizeof(T) == 4) ? 3 : 2;
+  T a[NBUF][RB][4];
   auto load = [&](T (&dst)[RB][4], int r0) {
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
@@ -390,13 +394,14 @@ __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A,
     for (int e = 0; e < 4; ++e) vjr[w][e] = vin[w][min(c0 + e, n - 1)];
     vrr[w] = vin[w][min(rw + lane, n - 1)];
   }
-  load(a[0], rw);
+#pragma unroll
+  for (int b = 0; b + 1 < NBUF; ++b) load(a[b], rw + b * RB);
   double vj[NV][4], vrow[NV];
 #pragma unroll
   for (int bt = 0; bt < NBT; ++bt) {
     // keep the scheduler from hoisting later batches' loads (they would need more buffers)
     __builtin_amdgcn_sched_barrier(0);
-    if (bt + 1 < NBT) load(a[(bt + 1) & 1], rw + (bt + 1) * RB);
+    if (bt + NBUF - 1 < NBT) load(a[(bt + NBUF - 1) % NBUF], rw + (bt + NBUF - 1) * RB);
     if (bt == 0) {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -412,7 +417,7 @@ __device__ __forceinline__ void gemv_stream(const gmem<const T>* __restrict__ A,
     for (int q = 0; q < RB; ++q) {
       double x[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) x[e] = (double)a[bt & 1][q][e];
+      for (int e = 0; e < 4; ++e) x[e] = (double)a[bt % NBUF][q][e];
 #pragma unroll
       for (int w = 0; w < NV; ++w) {
         rs[w][q] = x[0] * vj[w][0] + x[1] * vj[w][1] + x[2] * vj[w][2] + x[3] * vj[w][3];
